@@ -1,0 +1,83 @@
+/*
+ * Plain FP64 CPU oracle for the checkerboard SU(2)/SU(3) Wilson-action
+ * Monte Carlo (pseudo-heat bath, overrelaxation, reunitarisation, plaquette
+ * and Polyakov loop).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * path (the HIP library under paper_1310_7087_amd/) never links, loads or
+ * calls it, and shares no source, header or table with it.
+ *
+ * Everything is plain, unblocked FP64 in the canonical layout:
+ *   site i = x + Nx*(y + Ny*(z + Nz*t)),  parity (x+y+z+t) mod 2,
+ *   link (i, mu) at offset (i*4 + mu) * ncomp doubles,
+ *   SU(3): 18 doubles, row-major 3x3, (re, im) interleaved;
+ *   SU(2): 4 doubles, quaternion (a0,a1,a2,a3) = a0*1 + i(a1 s1 + a2 s2 + a3 s3).
+ * Exported links are in the "W-frame" (dynamical link times the fixed
+ * background field); internally the oracle keeps the U-frame and applies
+ * the background on the fly.
+ */
+#ifndef LAT_ORACLE_H
+#define LAT_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_lattice orc_lattice;
+
+enum { ORC_RNG_MRG32K3A = 0, ORC_RNG_PHILOX = 1, ORC_RNG_CONST = 2 };
+enum { ORC_COLD = 0, ORC_HOT = 1 };
+
+/* Returns NULL on invalid arguments (odd or < 2 extents, group not 2/3). */
+orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta,
+                        int flux, int rng, double rng_const, uint64_t seed,
+                        int nhit, uint32_t lattice_id, int start);
+void orc_destroy(orc_lattice* L);
+void orc_set_threads(int n);
+int  orc_get_threads(void);
+
+/* One compound sweep: n_hb heat-bath sweeps then n_or overrelaxation sweeps,
+ * every sweep = mu 0..3 x parity 0,1; each link reunitarised after its last
+ * update of the compound sweep. */
+void orc_sweep(orc_lattice* L, int n_hb, int n_or);
+/* plaq = {P, P_s, P_t}, poly = {Re L, Im L}. */
+void orc_measure(const orc_lattice* L, double plaq[3], double poly[2]);
+/* Canonical W-frame FP64 links, 4*V*ncomp doubles. */
+void orc_get_links(const orc_lattice* L, double* out);
+void orc_set_links(orc_lattice* L, const double* in);
+uint64_t orc_hb_sweeps(const orc_lattice* L);
+/* MRG32k3a per-site states, 6 words per site (x1[n-3],x1[n-2],x1[n-1],x2[...]). */
+int  orc_get_mrg_states(const orc_lattice* L, uint32_t* out);
+/* Accept log of the most recent compound sweep's heat-bath updates:
+ * one int8 per (hb sweep k, mu, site i, subgroup g), value = accepted try
+ * index or -1.  Layout [k][mu][i][g], g < 3.  Enabled by orc_enable_accept_log. */
+void orc_enable_accept_log(orc_lattice* L, int on);
+int64_t orc_get_accept_log(const orc_lattice* L, int8_t* out, int64_t n);
+
+/* ---- primitives exposed for pinning ---- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* State of site stream `site` for MRG32k3a seed s: A^(site*2^127) (s,s,s,s,s,s). */
+int  orc_mrg_site_state(uint64_t seed, uint64_t site, uint32_t st[6]);
+/* One MRG32k3a step; returns z in [1, m1]. */
+uint32_t orc_mrg_next(uint32_t st[6]);
+/* Advance a state by 2^e steps (matrix squaring), for jump checks. */
+void orc_mrg_advance_pow2(uint32_t st[6], int e);
+double orc_uniform24(uint32_t w);
+/* Kennedy-Pendleton draw at alpha from sequential uniforms u[]
+ * (4 per try, then 2 for the direction).  Returns the accepted try index or
+ * -1; x[4] = (a0,a1,a2,a3) or (1,0,0,0) if rejected. *used = uniforms read. */
+int  orc_kp_sample(double alpha, int nhit, const double* u, double x[4], int* used);
+/* Update one link with a fixed staple: kind 0 = heat bath, 1 = overrelaxation.
+ * U, Uout canonical (ncomp doubles); A is the staple as an N x N complex
+ * matrix, row-major (re,im).  u[] sequential uniforms as in orc_kp_sample.
+ * reunit != 0 reunitarises the result. Returns the number of uniforms read. */
+int  orc_update_link(int group, double beta, int nhit, int kind, int reunit,
+                     const double* U, const double* A, const double* u, double* Uout);
+/* Staple of link (i, mu) in the W-frame as an N x N complex matrix. */
+void orc_staple(const orc_lattice* L, int64_t i, int mu, double* A);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
