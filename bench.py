@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the checkerboard SU(3) Wilson-action sweep on one MI355X.
+
+A step is one working sweep of the whole hot path on SU(3) 32^3 x 8
+(beta 5.9, one flux quantum of the lambda_3 background, cold start): one
+compound sweep (1 heat-bath + 4 overrelaxation sweeps, reunitarisation
+fused into the last) followed by the plaquette and Polyakov-loop
+measurement.  The metric is link updates per second,
+steps * (1 + 4) * 4 V / time, with the lattice resident in HBM.
+
+Also reported: the FP32 and 12-real FP32 storage forms, the per-kernel
+roofline of the dominant pass kernel (event-timed in this run), and the FP64
+CPU oracle timed on a bounded sample of the same workload on the host cores.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+DIMS = (32, 32, 32, 8)
+BETA = 5.9
+FLUX = 1
+N_HB, N_OR = 1, 4
+BYTES_PER_LINK = {"f64": 144, "f32": 72, "f32c12": 48}
+KERNEL_SOURCES = ["paper_1310_7087_amd/csrc/lat_kernels.hip", "paper_1310_7087_amd/csrc/lat_dev.hpp",
+                  "paper_1310_7087_amd/csrc/lat_types.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_form(P, form: str, steps: int, warmup: int):
+    storage = {"f64": P.F64, "f32": P.F32, "f32c12": P.F32_C12}[form]
+    V = 1
+    for d in DIMS:
+        V *= d
+    lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage, rng=P.RNG_PHILOX, seed=3, start=P.COLD)
+    log(f"[{form}] warmup {warmup} steps")
+    lat.run(warmup, N_HB, N_OR, measure_every=1)
+    import torch
+    torch.cuda.synchronize()
+    log(f"[{form}] timing {steps} steps")
+    t0 = time.perf_counter()
+    plaq, poly = lat.run(steps, N_HB, N_OR, measure_every=1)  # queued on the device, synchronises
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    updates = steps * (N_HB + N_OR) * 4 * V
+    # event-timed passes of the same kernels on the same stream
+    t_hb, t_or = lat.profile_passes(N_HB, N_OR, reps=3)
+    b = BYTES_PER_LINK[form]
+    pass_bytes = 4.5 * V * b  # reads all 4V links, writes the V/2 updated ones
+    res = {
+        "link_updates_per_s": updates / dt,
+        "ms_per_step": 1e3 * dt / steps,
+        "plaquette_last": float(plaq[-1][0]),
+        "polyakov_last": [float(poly[-1][0]), float(poly[-1][1])],
+        "hb_pass_us": 1e3 * t_hb,
+        "or_pass_us": 1e3 * t_or,
+        "hb_pass_GBs": pass_bytes / (t_hb * 1e-3) / 1e9,
+        "or_pass_GBs": pass_bytes / (t_or * 1e-3) / 1e9,
+        "algorithmic_GBs": updates * 9 * b / dt / 1e9,
+        "pass_bytes": pass_bytes,
+    }
+    res["hbm_fraction"] = res["algorithmic_GBs"] / HBM_PEAK_GBS
+    lat.close()
+    return res
+
+
+def cpu_baseline(steps: int = 1):
+    import oracle as O
+    cores = len(os.sched_getaffinity(0))
+    O.set_threads(cores)
+    V = 1
+    for d in DIMS:
+        V *= d
+    ref = O.Lattice(3, DIMS, BETA, flux=FLUX, rng=O.RNG_PHILOX, seed=3, start=O.COLD)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ref.sweep(N_HB, N_OR)
+        ref.measure()
+    dt = time.perf_counter() - t0
+    return {"value": steps * (N_HB + N_OR) * 4 * V / dt, "unit": "link updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} step(s) (1 HB + 4 OR compound sweep + plaquette/Polyakov) of the same "
+                      f"SU(3) 32^3x8 lattice from the cold start, FP64, {cores} OpenMP threads",
+            "seconds": dt}
+
+
+def traffic_for(kernel: str, form: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, valid
+    only while the kernel sources are unchanged since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except ValueError:
+        return None
+    if data.get("kernel_hash") != kernel_hash():
+        return None
+    entry = data.get("kernels", {}).get(f"{form}:{kernel}")
+    return None if entry is None else entry.get("hbm_bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--forms", default="f64,f32,f32c12",
+                    help="storage forms to time; the first is the headline value")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the lattice is resident on a single MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    import paper_1310_7087_amd as P
+
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results = {}
+    for f in forms:
+        results[f] = run_form(P, f, args.steps, args.warmup)
+        log(f"[{f}] {results[f]['link_updates_per_s']:.3e} link updates/s, "
+            f"{results[f]['algorithmic_GBs']:.0f} GB/s algorithmic")
+    head = forms[0]
+    r = results[head]
+    V = 1
+    for d in DIMS:
+        V *= d
+    # dominant kernel: the pass kind with the larger share of a compound sweep
+    share_hb = N_HB * 8 * r["hb_pass_us"]
+    share_or = N_OR * 8 * r["or_pass_us"]
+    kname = "or_pass" if share_or >= share_hb else "hb_pass"
+    t_us = r[kname + "_us"]
+    achieved = r["pass_bytes"] / (t_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "kernel": f"su3_pass<{head},{'overrelax' if kname == 'or_pass' else 'heatbath'}>",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic_for(kname, head), "avg_launch_us": t_us,
+                "algorithmic_bytes_per_launch": r["pass_bytes"]}
+    out = {
+        "metric": "SU(3) link updates/s at 32^3x8 HB+OR",
+        "value": r["link_updates_per_s"],
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head,
+        "data": "synthetic",
+        "config": {"workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or_plus_measure",
+                   "lattice": list(DIMS), "beta": BETA, "flux_quanta": FLUX, "n_hb": N_HB, "n_or": N_OR,
+                   "storage": head, "parallelism": "single_gpu"},
+        "hbm_fraction_algorithmic": r["hbm_fraction"],
+        "roofline": roofline,
+        "forms": {f: {k: v for k, v in results[f].items() if k != "pass_bytes"} for f in forms},
+    }
+    if "f64" in results:
+        for f in forms:
+            if f != "f64":
+                out["forms"][f]["speedup_vs_f64"] = results[f]["link_updates_per_s"] / results["f64"]["link_updates_per_s"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,221 @@
+/*
+ * lat.h - C ABI of the MI355X lattice gauge Monte Carlo library (liblat.so).
+ *
+ * The library runs the checkerboard (even/odd) Wilson-action link sweep for
+ * SU(2) and SU(3) gauge fields on one AMD Instinct MI355X (gfx950): staple
+ * sum, SU(2) heat bath (Cabibbo-Marinari subgroups for SU(3)),
+ * overrelaxation, reunitarisation, per-site random streams, and the
+ * plaquette / Polyakov-loop reductions.  The problem statement follows the
+ * QCDGPU paper (arXiv:1310.7087): SU(N) gluodynamics in an external
+ * (chromo)magnetic field at finite temperature (abstract, Sec. 1 and 6);
+ * lattice geometry, gauge group and precision as build-time choices and the
+ * coupling and "magnetic field flux" as run-time parameters (Sec. 3.2);
+ * checkerboard (pseudo-)heat bath (Sec. 3.3); selectable generator with one
+ * seed parameter, 0 meaning "system time" (Sec. 3.4); hot start, NHIT = 10
+ * tries and reunitarisation (Sec. 5); periodic state saving (Sec. 3.1).
+ *
+ * Conventions shared by every call:
+ *   - Extents Nx, Ny, Nz, Nt are even and >= 2 (the checkerboard with
+ *     periodic boundaries requires even extents); mu = 0,1,2,3 = x,y,z,t.
+ *   - Canonical host link format ("W-frame"): FP64, site-major,
+ *     site i = x + Nx*(y + Ny*(z + Nz*t)), then mu, then components:
+ *       SU(3): 18 doubles, row-major 3x3, (re, im) interleaved;
+ *       SU(2): 4 doubles, quaternion (a0,a1,a2,a3) = a0 1 + i(a1 s1 + a2 s2 + a3 s3).
+ *     W = U * B contains the fixed background B of the flux (see lat_create).
+ *   - Every call returns an int status (LAT_OK = 0, negative on error);
+ *     lat_last_error() gives a message for the calling thread.
+ *   - A handle is not thread-safe; different handles may be used from
+ *     different threads.
+ *   - Work is queued on the handle's HIP stream: lat_sweep and lat_run (and
+ *     the batch equivalents) are asynchronous; lat_measure, lat_get_*,
+ *     lat_set_links and lat_save synchronise that stream.
+ */
+#ifndef LAT_H
+#define LAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define LAT_OK 0
+#define LAT_EINVAL (-1)       /* bad argument: odd/too small extent, group not 2|3,
+                                 beta < 0 or NaN, NULL output, wrong buffer size */
+#define LAT_ENOMEM (-2)       /* device or host allocation failed, or caller buffer too small */
+#define LAT_EDEVICE (-3)      /* a HIP call failed; the message names it */
+#define LAT_EIO (-4)          /* checkpoint file could not be read or written */
+#define LAT_ECORRUPT (-5)     /* checkpoint checksum or header mismatch */
+#define LAT_ESTATE (-6)       /* call not valid in the handle's current state */
+#define LAT_EUNSUPPORTED (-7) /* combination not supported (e.g. 12-real SU(2)) */
+
+/* ---- link storage forms ---- */
+#define LAT_F64 0      /* FP64, all reals stored (18 for SU(3), 4 for SU(2)) */
+#define LAT_F32 1      /* FP32 storage and staple/subgroup arithmetic; FP64 for
+                          reunitarisation, heat-bath acceptance and observable sums */
+#define LAT_F32_C12 2  /* as LAT_F32, SU(3) only: first two rows stored (12 reals),
+                          row 3 = conj(row1 x row2) rebuilt on every load */
+
+/* ---- random number generators (one parameter picks it, Sec. 3.4) ---- */
+#define LAT_RNG_MRG32K3A 0  /* per-site MRG32k3a streams, 2^127 apart */
+#define LAT_RNG_PHILOX 1    /* per-site counter-based Philox4x32-10 */
+#define LAT_RNG_CONST 2     /* every uniform = rng_const (debugging, Sec. 3.4) */
+
+#define LAT_COLD 0  /* unit links */
+#define LAT_HOT 1   /* Haar-random links */
+
+typedef struct lat_ctx* lat_t;
+typedef struct lat_batch* lat_batch_t;
+
+typedef struct {
+    int storage;         /* LAT_F64 (default), LAT_F32, LAT_F32_C12 */
+    int rng;             /* LAT_RNG_PHILOX (default), LAT_RNG_MRG32K3A, LAT_RNG_CONST */
+    double rng_const;    /* value of every uniform for LAT_RNG_CONST, in (0,1) */
+    int start;           /* LAT_HOT (default) or LAT_COLD */
+    uint64_t seed;       /* run seed; 0 = derived from the system time and reported
+                            by lat_get_info. MRG32k3a needs 1 <= seed < 4294944443. */
+    int nhit;            /* heat-bath tries per SU(2) (sub)update, 1..127; default 10 */
+    uint32_t lattice_id; /* second Philox counter word: distinguishes lattices
+                            that share a seed */
+    void* stream;        /* hipStream_t to queue work on (e.g. torch's current
+                            stream); NULL = a stream the library creates */
+    void* device_buffer; /* optional caller-owned device memory for all device
+                            state; it must stay alive until lat_destroy */
+    size_t device_bytes; /* its size; see lat_device_bytes */
+    int block_size;      /* work-group size of the sweep kernels: 0 = tuned
+                            default, else 64, 128, 256 or 512 */
+    int tile_order;      /* 0 = XCD-aware block->tile map (default),
+                            1 = identity, 2 = reversed (for order-independence tests) */
+} lat_options;
+
+/* Fills *opt with the defaults listed above. */
+void lat_default_options(lat_options* opt);
+
+/* Device bytes a lattice with these parameters needs (links, generator
+ * state, reduction scratch).  Returns 0 for invalid parameters. */
+size_t lat_device_bytes(int group, int Nx, int Ny, int Nz, int Nt, const lat_options* opt);
+
+/*
+ * Creates one lattice on the current HIP device and initialises it (cold or
+ * Haar-random links, times the background B).
+ *   group: 2 or 3 (SU(N)); beta: Wilson coupling >= 0.
+ *   field_flux: integer number n of flux quanta of a constant Abelian
+ *     chromomagnetic background along lambda_3 (T = diag(1,-1[,0])) through
+ *     the x-y planes: phi = 2 pi n / (Nx Ny) per x-y plaquette, realised by
+ *     the fixed links B_y(x) = exp(i phi x T) and, at x = Nx-1,
+ *     B_x(x) = exp(-i phi Nx y T).  The stored links are W = U B.
+ *   opt: NULL for defaults.  On success *out is a new handle.
+ */
+int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double beta,
+               int field_flux, const lat_options* opt);
+
+/*
+ * One compound sweep (asynchronous): n_hb heat-bath sweeps, then n_or
+ * overrelaxation sweeps.  Each sweep is 8 dependent checkerboard passes
+ * (mu = 0..3, parity 0 then 1).  Every link is reunitarised (in FP64) right
+ * after its last update of the compound sweep.  n_hb, n_or >= 0.
+ */
+int lat_sweep(lat_t h, int n_hb, int n_or);
+
+/*
+ * n_sweeps compound sweeps with a measurement after every measure_every-th
+ * one (0 = none), all queued without host synchronisation; the series are
+ * copied to the host at the end (this call synchronises).
+ *   plaq_series: [k][3] (P, P_s, P_t) or NULL; poly_series: [k][2] or NULL,
+ *   k = n_sweeps / measure_every measurements.
+ */
+int lat_run(lat_t h, int n_sweeps, int n_hb, int n_or, int measure_every,
+            double* plaq_series, double* poly_series);
+
+/*
+ * Measures (synchronously) the average plaquette
+ *   plaq[0] = P = (P_s + P_t)/2, plaq[1] = P_s (3 spatial planes),
+ *   plaq[2] = P_t (3 planes with t), each (1/N) Re Tr of
+ *   W_mu(x) W_nu(x+mu) W_mu(x+nu)^+ W_nu(x)^+,
+ * and the Polyakov loop poly = (Re, Im) of the spatial average of
+ *   (1/N) Tr prod_{t=0}^{Nt-1} W_t(x, t).
+ * Sums are FP64 with a compensated final reduction in a fixed order.
+ */
+int lat_measure(lat_t h, double plaq[3], double poly[2]);
+
+/* Canonical FP64 links (see top); n_doubles must equal 4*V*ncomp. */
+int lat_get_links(lat_t h, double* host, size_t n_doubles);
+/* Replaces all links (rounded to the storage form; 12-real keeps rows 1-2). */
+int lat_set_links(lat_t h, const double* host, size_t n_doubles);
+/* MRG32k3a per-site states in canonical site order, 6 words per site
+ * (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1]); n_words = 6*V.
+ * LAT_ESTATE for other generators. */
+int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words);
+/*
+ * Kernel profiling (the paper's run-time kernel profiling, Sec. 3.2): runs
+ * `reps` compound sweeps (n_hb, n_or) with every pass launched on its own
+ * between HIP events on the handle's stream, and returns the average
+ * duration in milliseconds of a heat-bath pass (ms_hb) and of an
+ * overrelaxation pass (ms_or).  The lattice advances as with lat_sweep.
+ * Synchronises.  Either output may be NULL.
+ */
+int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, double* ms_or);
+
+/* Any output pointer may be NULL. */
+int lat_get_info(lat_t h, uint64_t* seed_used, uint64_t* hb_sweeps_done, uint64_t* sweeps_done);
+
+/*
+ * Heat-bath accept log (debugging): when on, the next compound sweeps record
+ * for every heat-bath update the accepted try index (or -1 if all NHIT tries
+ * were rejected or the update was skipped), one int8 per
+ * [hb sweep k of the last compound sweep][mu][canonical site][subgroup g < 3].
+ * lat_get_accept_log copies min(n, available) bytes and returns that count
+ * (>= 0) or a negative status.
+ */
+int lat_set_accept_log(lat_t h, int on);
+int64_t lat_get_accept_log(lat_t h, int8_t* host, size_t n);
+
+/*
+ * Portable checkpoint (little-endian, checksummed): parameters, counters,
+ * canonical FP64 W-frame links and MRG32k3a states.  lat_load creates a new
+ * handle (storage and stream from opt, or the saved storage if opt is NULL)
+ * that continues the saved run exactly.
+ */
+int lat_save(lat_t h, const char* path);
+int lat_load(lat_t* out, const char* path, const lat_options* opt);
+
+/* Releases the handle; NULL is a no-op. */
+int lat_destroy(lat_t h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lat_last_error(void);
+
+/* Raw device Philox4x32-10 for generator checks: out[4k..4k+3] =
+ * Philox4x32-10(counter ctr[4k..4k+3], key); host arrays, n blocks. */
+int lat_philox4x32_10(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, size_t n);
+
+/* ------------------------------------------------------------------ */
+/* Batches: many independent lattices (a parameter scan, the paper's   */
+/* "trivial parallelisation", Sec. 5 and 6) advanced together by one   */
+/* persistent kernel launch per compound sweep.                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int group, Nx, Ny, Nz, Nt;
+    double beta;
+    int field_flux;
+    uint64_t seed;
+    int start;
+    uint32_t lattice_id;
+} lat_desc;
+
+/* n lattices described by d[0..n-1]; common supplies storage, rng (Philox or
+ * constant), nhit, stream (the per-lattice fields of common are ignored). */
+int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common);
+/* n_sweeps compound sweeps of every member; if plaq / poly are non-NULL they
+ * receive each member's final measurement ([n][3] and [n][2]); synchronises. */
+int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly);
+int lat_batch_get_links(lat_batch_t b, int i, double* host, size_t n_doubles);
+int lat_batch_set_links(lat_batch_t b, int i, const double* host, size_t n_doubles);
+int lat_batch_destroy(lat_batch_t b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAT_H */

@@ -1,0 +1,912 @@
+// Host runtime and C ABI of liblat.so (see include/lat.h).
+//
+// A lattice handle owns (or borrows from the caller) one device allocation
+// that holds the parity-split link planes, the per-site MRG32k3a states, the
+// heat-bath counter and the reduction scratch.  A compound sweep is captured
+// once per (n_hb, n_or) as a HIP graph of 8 * (n_hb + n_or) pass kernels and
+// replayed; steady-state sweeps never touch the host.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lat.h"
+#include "lat_launch.hpp"
+#include "lat_types.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(LAT_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                                   \
+    } while (0)
+
+constexpr uint64_t MRG_M1 = 4294967087ull;
+constexpr uint64_t MRG_M2 = 4294944443ull;
+constexpr int MEAS_CAPACITY = 4096;  // measurements buffered on the device per lat_run chunk
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- MRG32k3a jump-ahead on the host: 3x3 transition matrices mod m ----
+struct Mod3 {
+    uint64_t a[3][3];
+};
+uint64_t mulmod(uint64_t x, uint64_t y, uint64_t m) { return (x * y) % m; }  // x, y < 2^32
+Mod3 mod3_mul(const Mod3& x, const Mod3& y, uint64_t m) {
+    Mod3 r;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            uint64_t s = 0;
+            for (int k = 0; k < 3; ++k) s = (s + mulmod(x.a[i][k], y.a[k][j], m)) % m;
+            r.a[i][j] = s;
+        }
+    return r;
+}
+void mod3_apply(const Mod3& x, uint32_t* v, uint64_t m) {
+    uint64_t r[3];
+    for (int i = 0; i < 3; ++i) {
+        uint64_t s = 0;
+        for (int k = 0; k < 3; ++k) s = (s + mulmod(x.a[i][k], v[k], m)) % m;
+        r[i] = s;
+    }
+    for (int i = 0; i < 3; ++i) v[i] = (uint32_t)r[i];
+}
+// Per-site stream states: site i starts at A^(i * 2^127) (s,s,s,s,s,s).
+std::vector<uint32_t> mrg_site_states(uint64_t seed, int64_t nsites) {
+    Mod3 j1 = {{{0, 1, 0}, {0, 0, 1}, {MRG_M1 - 810728u, 1403580u, 0}}};
+    Mod3 j2 = {{{0, 1, 0}, {0, 0, 1}, {MRG_M2 - 1370589u, 0, 527612u}}};
+    for (int k = 0; k < 127; ++k) {
+        j1 = mod3_mul(j1, j1, MRG_M1);
+        j2 = mod3_mul(j2, j2, MRG_M2);
+    }
+    std::vector<uint32_t> out((size_t)nsites * 6);
+    uint32_t st[6];
+    for (int k = 0; k < 6; ++k) st[k] = (uint32_t)seed;
+    for (int64_t i = 0; i < nsites; ++i) {
+        std::memcpy(&out[(size_t)i * 6], st, sizeof st);
+        mod3_apply(j1, st, MRG_M1);
+        mod3_apply(j2, st + 3, MRG_M2);
+    }
+    return out;
+}
+
+int ncomp(int group) { return group == 3 ? 18 : 4; }
+size_t bytes_per_link(int group, int storage) {
+    if (group == 2) return storage == LAT_F64 ? 32 : 16;
+    return storage == LAT_F64 ? 144 : storage == LAT_F32 ? 72 : 48;
+}
+
+struct Layout {
+    LatGeom g;
+    size_t links_off, links_bytes;
+    size_t mrg_off, mrg_bytes;
+    size_t hb_off, slot_off;
+    size_t partial_off, partial_bytes;
+    size_t meas_off, meas_bytes;
+    size_t total;
+    int nb_plaq, nb_poly;
+};
+
+int make_layout(int group, const int d[4], int storage, int rng, Layout& L) {
+    for (int m = 0; m < 4; ++m)
+        if (d[m] < 2 || (d[m] & 1)) return fail(LAT_EINVAL, "extent %d = %d must be even and >= 2", m, d[m]);
+    if (group != 2 && group != 3) return fail(LAT_EINVAL, "group must be 2 or 3, got %d", group);
+    if (storage < LAT_F64 || storage > LAT_F32_C12) return fail(LAT_EINVAL, "unknown storage %d", storage);
+    if (group == 2 && storage == LAT_F32_C12) return fail(LAT_EUNSUPPORTED, "12-real storage is SU(3) only");
+    const int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
+    if (V / 2 > 0x7FFFFFFFLL) return fail(LAT_EINVAL, "lattice too large");
+    LatGeom g;
+    g.nx = d[0];
+    g.ny = d[1];
+    g.nz = d[2];
+    g.nt = d[3];
+    g.nxh = d[0] / 2;
+    g.vh = V / 2;
+    // equal plane lengths, padded to the work-group multiple
+    g.vh_pad = (int64_t)align_up((size_t)g.vh, 256);
+    L.g = g;
+    L.links_off = 0;
+    L.links_bytes = (size_t)g.vh_pad * 2 * 4 * bytes_per_link(group, storage);
+    size_t off = align_up(L.links_bytes, 4096);
+    L.mrg_off = off;
+    L.mrg_bytes = rng == LAT_RNG_MRG32K3A ? (size_t)g.vh_pad * 2 * 6 * 4 : 0;
+    off = align_up(off + L.mrg_bytes, 256);
+    L.hb_off = off;
+    off += 256;
+    L.slot_off = off;
+    off += 256;
+    L.nb_plaq = (int)((g.vh + 255) / 256);
+    const int64_t vs = (int64_t)d[0] * d[1] * d[2];
+    L.nb_poly = (int)((vs + 255) / 256);
+    L.partial_off = off;
+    L.partial_bytes = (size_t)(4 * L.nb_plaq + 2 * L.nb_poly) * sizeof(double);
+    off = align_up(off + L.partial_bytes, 256);
+    L.meas_off = off;
+    L.meas_bytes = (size_t)MEAS_CAPACITY * 5 * sizeof(double);
+    off = align_up(off + L.meas_bytes, 256);
+    L.total = off;
+    return LAT_OK;
+}
+
+}  // namespace
+
+struct lat_ctx {
+    int group = 3, storage = LAT_F64, rng = LAT_RNG_PHILOX, start = LAT_HOT, nhit = 10, flux = 0;
+    double beta = 0.0, rng_const = 0.5;
+    uint64_t seed = 0;
+    uint32_t lat_id = 0;
+    int dims[4] = {0, 0, 0, 0};
+    Layout lay;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* base = nullptr;
+    bool own_mem = false;
+    int block = 256;
+    int tile_order = 0;
+    uint64_t hb_sweeps = 0, sweeps = 0;
+    bool log_on = false;
+    int8_t* accept_log = nullptr;
+    size_t accept_bytes = 0;
+    size_t accept_valid = 0;
+    std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+
+    char* links() const { return base + lay.links_off; }
+    uint32_t* mrg() const { return lay.mrg_bytes ? reinterpret_cast<uint32_t*>(base + lay.mrg_off) : nullptr; }
+    uint64_t* hb() const { return reinterpret_cast<uint64_t*>(base + lay.hb_off); }
+    uint32_t* slot() const { return reinterpret_cast<uint32_t*>(base + lay.slot_off); }
+    double* partial() const { return reinterpret_cast<double*>(base + lay.partial_off); }
+    double* meas() const { return reinterpret_cast<double*>(base + lay.meas_off); }
+    int64_t V() const { return 2 * lay.g.vh; }
+    size_t n_doubles() const { return (size_t)V() * 4 * ncomp(group); }
+};
+
+namespace {
+
+void drop_graphs(lat_ctx* h) {
+    for (auto& kv : h->graphs) {
+        hipGraphExecDestroy(kv.second.second);
+        hipGraphDestroy(kv.second.first);
+    }
+    h->graphs.clear();
+}
+
+PassArgs pass_args(const lat_ctx* h) {
+    PassArgs a;
+    a.g = h->lay.g;
+    a.links = h->links();
+    a.mrg = h->mrg();
+    a.hb_count = h->hb();
+    a.accept_log = h->log_on ? h->accept_log : nullptr;
+    a.beta = h->beta;
+    a.rng_const = h->rng_const;
+    a.key0 = (uint32_t)h->seed;
+    a.key1 = (uint32_t)(h->seed >> 32);
+    a.lat_id = h->lat_id;
+    a.nhit = h->nhit;
+    a.group = h->group;
+    a.mu = 0;
+    a.parity = 0;
+    a.hb_offset = 0;
+    a.tile_order = h->tile_order;
+    a.flux = h->flux;
+    return a;
+}
+
+// Queue one compound sweep on the handle's stream.
+int enqueue_sweep(lat_ctx* h, int n_hb, int n_or) {
+    const int total = n_hb + n_or;
+    PassArgs a = pass_args(h);
+    for (int s = 0; s < total; ++s) {
+        const int kind = s < n_hb ? 0 : 1;
+        const bool reunit = (s == total - 1);
+        a.hb_offset = kind == 0 ? s : 0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p) {
+                a.mu = mu;
+                a.parity = p;
+                HIP_TRY(lat_launch_pass(h->group, h->storage, kind, reunit, h->rng, a, h->block, h->stream));
+            }
+    }
+    if (n_hb > 0) HIP_TRY(lat_launch_bump(h->hb(), n_hb, h->stream));
+    return LAT_OK;
+}
+
+int get_graph(lat_ctx* h, int n_hb, int n_or, hipGraphExec_t* out) {
+    auto key = std::make_pair(n_hb, n_or);
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        *out = it->second.second;
+        return LAT_OK;
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_sweep(h, n_hb, n_or);
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (rc != LAT_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return fail(LAT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    h->graphs[key] = std::make_pair(graph, exec);
+    *out = exec;
+    return LAT_OK;
+}
+
+int ensure_accept_log(lat_ctx* h, int n_hb) {
+    if (!h->log_on) return LAT_OK;
+    const size_t need = (size_t)n_hb * 4 * (size_t)h->V() * 3;
+    if (need > h->accept_bytes) {
+        if (h->accept_log) HIP_TRY(hipFree(h->accept_log));
+        h->accept_log = nullptr;
+        h->accept_bytes = 0;
+        HIP_TRY(hipMalloc(&h->accept_log, need));
+        h->accept_bytes = need;
+        drop_graphs(h);  // captured graphs hold the old pointer
+    }
+    if (need) HIP_TRY(hipMemsetAsync(h->accept_log, 0xFF, need, h->stream));
+    h->accept_valid = need;
+    return LAT_OK;
+}
+
+int do_sweep(lat_ctx* h, int n_hb, int n_or) {
+    if (n_hb + n_or == 0) return LAT_OK;
+    int rc = ensure_accept_log(h, n_hb);
+    if (rc) return rc;
+    hipGraphExec_t ex;
+    rc = get_graph(h, n_hb, n_or, &ex);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(ex, h->stream));
+    h->hb_sweeps += (uint64_t)n_hb;
+    h->sweeps += 1;
+    return LAT_OK;
+}
+
+int enqueue_measure(lat_ctx* h, bool series) {
+    MeasArgs m;
+    m.g = h->lay.g;
+    m.links = h->links();
+    m.partial = h->partial();
+    m.nb_plaq = h->lay.nb_plaq;
+    m.nb_poly = h->lay.nb_poly;
+    HIP_TRY(lat_launch_measure(h->group, h->storage, m, h->meas(), series ? h->slot() : nullptr, h->stream));
+    return LAT_OK;
+}
+
+uint64_t time_seed() {
+    uint64_t t = (uint64_t)std::chrono::high_resolution_clock::now().time_since_epoch().count();
+    t ^= t >> 29;
+    return t ? t : 1;
+}
+
+int init_handle(lat_ctx* h, const lat_options* opt) {
+    HIP_TRY(hipGetDevice(&h->device));
+    if (opt->stream) {
+        h->stream = (hipStream_t)opt->stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    if (opt->device_buffer) {
+        if (opt->device_bytes < h->lay.total)
+            return fail(LAT_ENOMEM, "caller buffer of %zu bytes, need %zu", opt->device_bytes, h->lay.total);
+        if (((uintptr_t)opt->device_buffer) & 255) return fail(LAT_EINVAL, "device_buffer must be 256-byte aligned");
+        h->base = (char*)opt->device_buffer;
+    } else {
+        hipError_t e = hipMalloc(&h->base, h->lay.total);
+        if (e != hipSuccess) return fail(LAT_ENOMEM, "hipMalloc(%zu): %s", h->lay.total, hipGetErrorString(e));
+        h->own_mem = true;
+    }
+    // counters start at zero
+    std::vector<uint8_t> zero(512, 0);
+    HIP_TRY(hipMemcpyAsync(h->base + h->lay.hb_off, zero.data(), 512, hipMemcpyHostToDevice, h->stream));
+    if (h->rng == LAT_RNG_MRG32K3A) {
+        // canonical per-site states -> [parity][word][half index]
+        std::vector<uint32_t> canon = mrg_site_states(h->seed, h->V());
+        const LatGeom& g = h->lay.g;
+        std::vector<uint32_t> dev((size_t)g.vh_pad * 12, 0);
+        for (int64_t i = 0; i < h->V(); ++i) {
+            int64_t r = i;
+            const int x = (int)(r % g.nx); r /= g.nx;
+            const int y = (int)(r % g.ny); r /= g.ny;
+            const int z = (int)(r % g.nz);
+            const int t = (int)(r / g.nz);
+            const int p = (x + y + z + t) & 1;
+            const int64_t s = (x >> 1) + (int64_t)g.nxh * (y + (int64_t)g.ny * (z + (int64_t)g.nz * t));
+            for (int w = 0; w < 6; ++w) dev[((size_t)p * 6 + w) * g.vh_pad + s] = canon[(size_t)i * 6 + w];
+        }
+        HIP_TRY(hipMemcpyAsync(h->mrg(), dev.data(), dev.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    InitArgs ia;
+    ia.g = h->lay.g;
+    ia.links = h->links();
+    ia.mrg = h->mrg();
+    ia.rng_const = h->rng_const;
+    ia.key0 = (uint32_t)h->seed;
+    ia.key1 = (uint32_t)(h->seed >> 32);
+    ia.lat_id = h->lat_id;
+    ia.start = h->start;
+    ia.flux = h->flux;
+    HIP_TRY(lat_launch_init(h->group, h->storage, h->rng, ia, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LAT_OK;
+}
+
+int check_opts(const lat_options* o) {
+    if (o->rng < LAT_RNG_MRG32K3A || o->rng > LAT_RNG_CONST) return fail(LAT_EINVAL, "unknown rng %d", o->rng);
+    if (o->rng == LAT_RNG_CONST && !(o->rng_const > 0.0 && o->rng_const < 1.0))
+        return fail(LAT_EINVAL, "rng_const must lie in (0,1)");
+    if (o->start != LAT_COLD && o->start != LAT_HOT) return fail(LAT_EINVAL, "unknown start %d", o->start);
+    if (o->nhit < 1 || o->nhit > 127) return fail(LAT_EINVAL, "nhit must be in 1..127");
+    if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 && o->block_size != 256)
+        return fail(LAT_EINVAL, "block_size must be 0, 64, 128 or 256");
+    if (o->tile_order < 0 || o->tile_order > 2) return fail(LAT_EINVAL, "tile_order must be 0, 1 or 2");
+    return LAT_OK;
+}
+
+void destroy_handle(lat_ctx* h) {
+    if (!h) return;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->accept_log) hipFree(h->accept_log);
+    if (h->own_mem && h->base) hipFree(h->base);
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    delete h;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void lat_default_options(lat_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->storage = LAT_F64;
+    o->rng = LAT_RNG_PHILOX;
+    o->rng_const = 0.5;
+    o->start = LAT_HOT;
+    o->seed = 0;
+    o->nhit = 10;
+    o->lattice_id = 0;
+    o->block_size = 0;
+    o->tile_order = 0;
+}
+
+const char* lat_last_error(void) { return g_err.c_str(); }
+
+size_t lat_device_bytes(int group, int Nx, int Ny, int Nz, int Nt, const lat_options* opt) {
+    lat_options o;
+    lat_default_options(&o);
+    if (opt) o = *opt;
+    int d[4] = {Nx, Ny, Nz, Nt};
+    Layout L;
+    if (make_layout(group, d, o.storage, o.rng, L) != LAT_OK) return 0;
+    return L.total;
+}
+
+int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double beta, int field_flux,
+               const lat_options* opt) {
+    g_err.clear();
+    if (!out) return fail(LAT_EINVAL, "out is NULL");
+    *out = nullptr;
+    lat_options o;
+    lat_default_options(&o);
+    if (opt) o = *opt;
+    if (!(beta >= 0.0) || beta > 1e6) return fail(LAT_EINVAL, "beta must be finite and >= 0");
+    int rc = check_opts(&o);
+    if (rc) return rc;
+    lat_ctx* h = new lat_ctx();
+    h->group = group;
+    h->storage = o.storage;
+    h->rng = o.rng;
+    h->rng_const = o.rng_const;
+    h->start = o.start;
+    h->nhit = o.nhit;
+    h->flux = field_flux;
+    h->beta = beta;
+    h->lat_id = o.lattice_id;
+    h->block = o.block_size ? o.block_size : 256;
+    h->tile_order = o.tile_order;
+    h->dims[0] = Nx;
+    h->dims[1] = Ny;
+    h->dims[2] = Nz;
+    h->dims[3] = Nt;
+    rc = make_layout(group, h->dims, o.storage, o.rng, h->lay);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    uint64_t seed = o.seed;
+    if (seed == 0) {
+        seed = time_seed();
+        if (o.rng == LAT_RNG_MRG32K3A) seed = 1 + seed % (MRG_M2 - 1);
+    }
+    if (o.rng == LAT_RNG_MRG32K3A && (seed < 1 || seed >= MRG_M2)) {
+        delete h;
+        return fail(LAT_EINVAL, "MRG32k3a seed must be in [1, 4294944443)");
+    }
+    h->seed = seed;
+    rc = init_handle(h, &o);
+    if (rc) {
+        std::string keep = g_err;
+        destroy_handle(h);
+        g_err = keep;
+        return rc;
+    }
+    *out = h;
+    return LAT_OK;
+}
+
+int lat_destroy(lat_t h) {
+    destroy_handle(h);
+    return LAT_OK;
+}
+
+int lat_sweep(lat_t h, int n_hb, int n_or) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if (n_hb < 0 || n_or < 0) return fail(LAT_EINVAL, "negative sweep count");
+    return do_sweep(h, n_hb, n_or);
+}
+
+int lat_measure(lat_t h, double plaq[3], double poly[2]) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if (!plaq && !poly) return fail(LAT_EINVAL, "no output");
+    int rc = enqueue_measure(h, false);
+    if (rc) return rc;
+    double r[5];
+    HIP_TRY(hipMemcpyAsync(r, h->meas(), sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (plaq) std::memcpy(plaq, r, 3 * sizeof(double));
+    if (poly) std::memcpy(poly, r + 3, 2 * sizeof(double));
+    return LAT_OK;
+}
+
+int lat_run(lat_t h, int n_sweeps, int n_hb, int n_or, int measure_every, double* plaq_series,
+            double* poly_series) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if (n_sweeps < 0 || n_hb < 0 || n_or < 0 || measure_every < 0) return fail(LAT_EINVAL, "negative argument");
+    int done = 0;  // measurements copied out so far
+    int pending = 0;
+    static const uint32_t zero = 0;
+    HIP_TRY(hipMemcpyAsync(h->slot(), &zero, sizeof zero, hipMemcpyHostToDevice, h->stream));
+    auto flush = [&]() -> int {
+        if (!pending) return LAT_OK;
+        std::vector<double> buf((size_t)pending * 5);
+        HIP_TRY(hipMemcpyAsync(buf.data(), h->meas(), buf.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        for (int k = 0; k < pending; ++k) {
+            if (plaq_series) std::memcpy(plaq_series + 3 * (size_t)(done + k), &buf[5 * (size_t)k], 3 * sizeof(double));
+            if (poly_series) std::memcpy(poly_series + 2 * (size_t)(done + k), &buf[5 * (size_t)k + 3], 2 * sizeof(double));
+        }
+        done += pending;
+        pending = 0;
+        HIP_TRY(hipMemcpyAsync(h->slot(), &zero, sizeof zero, hipMemcpyHostToDevice, h->stream));
+        return LAT_OK;
+    };
+    for (int k = 0; k < n_sweeps; ++k) {
+        int rc = do_sweep(h, n_hb, n_or);
+        if (rc) return rc;
+        if (measure_every > 0 && (k + 1) % measure_every == 0) {
+            rc = enqueue_measure(h, true);
+            if (rc) return rc;
+            if (++pending == MEAS_CAPACITY) {
+                rc = flush();
+                if (rc) return rc;
+            }
+        }
+    }
+    int rc = flush();
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LAT_OK;
+}
+
+int lat_get_links(lat_t h, double* host, size_t n_doubles) {
+    if (!h || !host) return fail(LAT_EINVAL, "NULL argument");
+    if (n_doubles != h->n_doubles()) return fail(LAT_EINVAL, "need %zu doubles, got %zu", h->n_doubles(), n_doubles);
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, n_doubles * sizeof(double)));
+    hipError_t e = lat_launch_convert(h->group, h->storage, false, h->lay.g, tmp, h->links(), h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, n_doubles * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_get_links: %s", hipGetErrorString(e));
+    return LAT_OK;
+}
+
+int lat_set_links(lat_t h, const double* host, size_t n_doubles) {
+    if (!h || !host) return fail(LAT_EINVAL, "NULL argument");
+    if (n_doubles != h->n_doubles()) return fail(LAT_EINVAL, "need %zu doubles, got %zu", h->n_doubles(), n_doubles);
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, n_doubles * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(tmp, host, n_doubles * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = lat_launch_convert(h->group, h->storage, true, h->lay.g, tmp, h->links(), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_set_links: %s", hipGetErrorString(e));
+    return LAT_OK;
+}
+
+int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words) {
+    if (!h || !host) return fail(LAT_EINVAL, "NULL argument");
+    if (h->rng != LAT_RNG_MRG32K3A) return fail(LAT_ESTATE, "generator has no per-site state");
+    if (n_words != (size_t)h->V() * 6) return fail(LAT_EINVAL, "need %lld words", (long long)(h->V() * 6));
+    const LatGeom& g = h->lay.g;
+    std::vector<uint32_t> dev((size_t)g.vh_pad * 12);
+    HIP_TRY(hipMemcpyAsync(dev.data(), h->mrg(), dev.size() * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < h->V(); ++i) {
+        int64_t r = i;
+        const int x = (int)(r % g.nx); r /= g.nx;
+        const int y = (int)(r % g.ny); r /= g.ny;
+        const int z = (int)(r % g.nz);
+        const int t = (int)(r / g.nz);
+        const int p = (x + y + z + t) & 1;
+        const int64_t s = (x >> 1) + (int64_t)g.nxh * (y + (int64_t)g.ny * (z + (int64_t)g.nz * t));
+        for (int w = 0; w < 6; ++w) host[(size_t)i * 6 + w] = dev[((size_t)p * 6 + w) * g.vh_pad + s];
+    }
+    return LAT_OK;
+}
+
+int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, double* ms_or) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if (n_hb < 0 || n_or < 0 || reps < 1 || n_hb + n_or == 0) return fail(LAT_EINVAL, "bad profile arguments");
+    if (h->log_on) return fail(LAT_ESTATE, "switch the accept log off before profiling");
+    const int total = n_hb + n_or;
+    const int npass = 8 * total;
+    std::vector<hipEvent_t> ev((size_t)npass * reps + 1);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    PassArgs a = pass_args(h);
+    int k = 0;
+    HIP_TRY(hipEventRecord(ev[k++], h->stream));
+    for (int r = 0; r < reps; ++r) {
+        for (int s = 0; s < total; ++s) {
+            const int kind = s < n_hb ? 0 : 1;
+            a.hb_offset = kind == 0 ? s : 0;
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p) {
+                    a.mu = mu;
+                    a.parity = p;
+                    HIP_TRY(lat_launch_pass(h->group, h->storage, kind, s == total - 1, h->rng, a, h->block,
+                                            h->stream));
+                    HIP_TRY(hipEventRecord(ev[k++], h->stream));
+                }
+        }
+        if (n_hb > 0) HIP_TRY(lat_launch_bump(h->hb(), n_hb, h->stream));
+        h->hb_sweeps += (uint64_t)n_hb;
+        h->sweeps += 1;
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    double sum_hb = 0.0, sum_or = 0.0;
+    k = 0;
+    for (int r = 0; r < reps; ++r)
+        for (int s = 0; s < total; ++s)
+            for (int j = 0; j < 8; ++j) {
+                float ms = 0.f;
+                // the event after the previous pass starts this pass's interval; the
+                // first pass of a repetition after a counter bump starts at the bump
+                HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+                ++k;
+                (s < n_hb ? sum_hb : sum_or) += ms;
+            }
+    for (auto& e : ev) hipEventDestroy(e);
+    if (ms_hb) *ms_hb = n_hb ? sum_hb / (8.0 * n_hb * reps) : 0.0;
+    if (ms_or) *ms_or = n_or ? sum_or / (8.0 * n_or * reps) : 0.0;
+    return LAT_OK;
+}
+
+int lat_get_info(lat_t h, uint64_t* seed_used, uint64_t* hb_sweeps_done, uint64_t* sweeps_done) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if (seed_used) *seed_used = h->seed;
+    if (hb_sweeps_done) *hb_sweeps_done = h->hb_sweeps;
+    if (sweeps_done) *sweeps_done = h->sweeps;
+    return LAT_OK;
+}
+
+int lat_set_accept_log(lat_t h, int on) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if ((on != 0) != h->log_on) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        drop_graphs(h);
+        h->log_on = on != 0;
+        h->accept_valid = 0;
+    }
+    return LAT_OK;
+}
+
+int64_t lat_get_accept_log(lat_t h, int8_t* host, size_t n) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    const size_t m = n < h->accept_valid ? n : h->accept_valid;
+    if (m) {
+        if (!host) return fail(LAT_EINVAL, "NULL output");
+        HIP_TRY(hipMemcpyAsync(host, h->accept_log, m, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return (int64_t)m;
+}
+
+int lat_philox4x32_10(const uint32_t* ctr, const uint32_t key[2], uint32_t* out, size_t n) {
+    if (!ctr || !key || !out) return fail(LAT_EINVAL, "NULL argument");
+    if (n == 0) return LAT_OK;
+    uint32_t *dc = nullptr, *dout = nullptr;
+    HIP_TRY(hipMalloc(&dc, n * 16));
+    hipError_t e = hipMalloc(&dout, n * 16);
+    if (e == hipSuccess) e = hipMemcpy(dc, ctr, n * 16, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = lat_launch_philox(dc, key[0], key[1], dout, (int64_t)n, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, n * 16, hipMemcpyDeviceToHost);
+    hipFree(dc);
+    if (dout) hipFree(dout);
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_philox4x32_10: %s", hipGetErrorString(e));
+    return LAT_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// checkpoint
+// ===========================================================================
+namespace {
+
+const char CKPT_MAGIC[8] = {'L', 'A', 'T', 'C', 'K', 'P', 'T', '1'};
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, group, dims[4], storage, rng, start, nhit;
+    int32_t flux;
+    uint32_t lat_id;
+    double beta, rng_const;
+    uint64_t seed, hb_sweeps, sweeps, n_doubles, n_mrg;
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" int lat_save(lat_t h, const char* path) {
+    if (!h || !path) return fail(LAT_EINVAL, "NULL argument");
+    std::vector<double> links(h->n_doubles());
+    int rc = lat_get_links(h, links.data(), links.size());
+    if (rc) return rc;
+    std::vector<uint32_t> mrg;
+    if (h->rng == LAT_RNG_MRG32K3A) {
+        mrg.resize((size_t)h->V() * 6);
+        rc = lat_get_rng_state(h, mrg.data(), mrg.size());
+        if (rc) return rc;
+    }
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, CKPT_MAGIC, 8);
+    hd.version = 1;
+    hd.group = (uint32_t)h->group;
+    for (int m = 0; m < 4; ++m) hd.dims[m] = (uint32_t)h->dims[m];
+    hd.storage = (uint32_t)h->storage;
+    hd.rng = (uint32_t)h->rng;
+    hd.start = (uint32_t)h->start;
+    hd.nhit = (uint32_t)h->nhit;
+    hd.flux = h->flux;
+    hd.lat_id = h->lat_id;
+    hd.beta = h->beta;
+    hd.rng_const = h->rng_const;
+    hd.seed = h->seed;
+    hd.hb_sweeps = h->hb_sweeps;
+    hd.sweeps = h->sweeps;
+    hd.n_doubles = links.size();
+    hd.n_mrg = mrg.size();
+    uint64_t sum = 1469598103934665603ull;
+    sum = fnv1a(sum, &hd, sizeof hd);
+    sum = fnv1a(sum, links.data(), links.size() * sizeof(double));
+    if (!mrg.empty()) sum = fnv1a(sum, mrg.data(), mrg.size() * 4);
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(LAT_EIO, "cannot open %s", tmp.c_str());
+    bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1;
+    ok = ok && std::fwrite(links.data(), sizeof(double), links.size(), f) == links.size();
+    if (!mrg.empty()) ok = ok && std::fwrite(mrg.data(), 4, mrg.size(), f) == mrg.size();
+    ok = ok && std::fwrite(&sum, sizeof sum, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(LAT_EIO, "write of %s failed", path);
+    }
+    return LAT_OK;
+}
+
+extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
+    if (!out || !path) return fail(LAT_EINVAL, "NULL argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(LAT_EIO, "cannot open %s", path);
+    CkptHeader hd;
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0 || hd.version != 1) {
+        std::fclose(f);
+        return fail(LAT_ECORRUPT, "%s is not a lattice checkpoint", path);
+    }
+    const uint64_t V = (uint64_t)hd.dims[0] * hd.dims[1] * hd.dims[2] * hd.dims[3];
+    if ((hd.group != 2 && hd.group != 3) || hd.n_doubles != V * 4 * (uint64_t)ncomp((int)hd.group) ||
+        (hd.n_mrg != 0 && hd.n_mrg != V * 6)) {
+        std::fclose(f);
+        return fail(LAT_ECORRUPT, "inconsistent checkpoint header in %s", path);
+    }
+    std::vector<double> links(hd.n_doubles);
+    std::vector<uint32_t> mrg(hd.n_mrg);
+    uint64_t stored = 0;
+    bool ok = std::fread(links.data(), sizeof(double), links.size(), f) == links.size();
+    if (!mrg.empty()) ok = ok && std::fread(mrg.data(), 4, mrg.size(), f) == mrg.size();
+    ok = ok && std::fread(&stored, sizeof stored, 1, f) == 1;
+    std::fclose(f);
+    if (!ok) return fail(LAT_ECORRUPT, "%s is truncated", path);
+    uint64_t sum = 1469598103934665603ull;
+    sum = fnv1a(sum, &hd, sizeof hd);
+    sum = fnv1a(sum, links.data(), links.size() * sizeof(double));
+    if (!mrg.empty()) sum = fnv1a(sum, mrg.data(), mrg.size() * 4);
+    if (sum != stored) return fail(LAT_ECORRUPT, "checksum mismatch in %s", path);
+
+    lat_options o;
+    lat_default_options(&o);
+    if (opt) o = *opt;
+    else o.storage = (int)hd.storage;
+    o.rng = (int)hd.rng;
+    o.rng_const = hd.rng_const;
+    o.start = LAT_COLD;
+    o.seed = hd.seed;
+    o.nhit = (int)hd.nhit;
+    o.lattice_id = hd.lat_id;
+    lat_t h = nullptr;
+    int rc = lat_create(&h, (int)hd.group, (int)hd.dims[0], (int)hd.dims[1], (int)hd.dims[2], (int)hd.dims[3],
+                        hd.beta, hd.flux, &o);
+    if (rc) return rc;
+    h->start = (int)hd.start;
+    rc = lat_set_links(h, links.data(), links.size());
+    if (!rc && !mrg.empty()) {
+        const LatGeom& g = h->lay.g;
+        std::vector<uint32_t> dev((size_t)g.vh_pad * 12, 0);
+        for (int64_t i = 0; i < h->V(); ++i) {
+            int64_t r = i;
+            const int x = (int)(r % g.nx); r /= g.nx;
+            const int y = (int)(r % g.ny); r /= g.ny;
+            const int z = (int)(r % g.nz);
+            const int t = (int)(r / g.nz);
+            const int p = (x + y + z + t) & 1;
+            const int64_t s = (x >> 1) + (int64_t)g.nxh * (y + (int64_t)g.ny * (z + (int64_t)g.nz * t));
+            for (int w = 0; w < 6; ++w) dev[((size_t)p * 6 + w) * g.vh_pad + s] = mrg[(size_t)i * 6 + w];
+        }
+        hipError_t e = hipMemcpy(h->mrg(), dev.data(), dev.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(LAT_EDEVICE, "restore of generator state: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        h->hb_sweeps = hd.hb_sweeps;
+        h->sweeps = hd.sweeps;
+        hipError_t e = hipMemcpy(h->hb(), &hd.hb_sweeps, sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(LAT_EDEVICE, "restore of counters: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        std::string keep = g_err;
+        destroy_handle(h);
+        g_err = keep;
+        return rc;
+    }
+    *out = h;
+    return LAT_OK;
+}
+
+// ===========================================================================
+// batches: independent lattices, one handle each, swept together
+// ===========================================================================
+struct lat_batch {
+    std::vector<lat_t> members;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+};
+
+extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common) {
+    if (!out || !d || n <= 0) return fail(LAT_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    lat_options o;
+    lat_default_options(&o);
+    if (common) o = *common;
+    lat_batch* b = new lat_batch();
+    if (o.stream) {
+        b->stream = (hipStream_t)o.stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(LAT_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        b->own_stream = true;
+    }
+    for (int i = 0; i < n; ++i) {
+        lat_options mo = o;
+        mo.stream = b->stream;
+        mo.device_buffer = nullptr;
+        mo.device_bytes = 0;
+        mo.seed = d[i].seed;
+        mo.start = d[i].start;
+        mo.lattice_id = d[i].lattice_id;
+        lat_t h = nullptr;
+        int rc = lat_create(&h, d[i].group, d[i].Nx, d[i].Ny, d[i].Nz, d[i].Nt, d[i].beta, d[i].field_flux, &mo);
+        if (rc) {
+            std::string keep = g_err;
+            lat_batch_destroy(b);
+            g_err = "batch member " + std::to_string(i) + ": " + keep;
+            return rc;
+        }
+        b->members.push_back(h);
+    }
+    *out = b;
+    return LAT_OK;
+}
+
+extern "C" int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly) {
+    if (!b) return fail(LAT_EINVAL, "NULL batch");
+    if (n_sweeps < 0 || n_hb < 0 || n_or < 0) return fail(LAT_EINVAL, "negative argument");
+    for (int k = 0; k < n_sweeps; ++k)
+        for (lat_t h : b->members) {
+            int rc = do_sweep(h, n_hb, n_or);
+            if (rc) return rc;
+        }
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        if (plaq || poly) {
+            int rc = lat_measure(b->members[i], plaq ? plaq + 3 * i : nullptr, poly ? poly + 2 * i : nullptr);
+            if (rc) return rc;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return LAT_OK;
+}
+
+extern "C" int lat_batch_get_links(lat_batch_t b, int i, double* host, size_t n) {
+    if (!b || i < 0 || i >= (int)b->members.size()) return fail(LAT_EINVAL, "bad batch index");
+    return lat_get_links(b->members[i], host, n);
+}
+
+extern "C" int lat_batch_set_links(lat_batch_t b, int i, const double* host, size_t n) {
+    if (!b || i < 0 || i >= (int)b->members.size()) return fail(LAT_EINVAL, "bad batch index");
+    return lat_set_links(b->members[i], host, n);
+}
+
+extern "C" int lat_batch_destroy(lat_batch_t b) {
+    if (!b) return LAT_OK;
+    for (lat_t h : b->members) lat_destroy(h);
+    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    delete b;
+    return LAT_OK;
+}

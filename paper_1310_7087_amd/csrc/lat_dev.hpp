@@ -1,0 +1,463 @@
+// Device-side building blocks for gfx950: complex SU(3) and quaternion SU(2)
+// algebra, the per-site random streams and the parity-split link layout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lat_types.hpp"
+
+#define LAT_DEV __device__ __forceinline__
+
+namespace latdev {
+
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------------------
+// complex numbers and 3x3 matrices (row-major)
+// ---------------------------------------------------------------------------
+template <class T>
+struct cx {
+    T re, im;
+};
+template <class T>
+LAT_DEV cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T>
+LAT_DEV cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T>
+LAT_DEV cx<T> cmul(cx<T> a, cx<T> b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// conj(a) * b
+template <class T>
+LAT_DEV cx<T> cjmul(cx<T> a, cx<T> b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
+// a * conj(b)
+template <class T>
+LAT_DEV cx<T> cmulj(cx<T> a, cx<T> b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }
+template <class T>
+LAT_DEV cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+
+template <class T>
+struct m3 {
+    cx<T> e[3][3];
+};
+
+template <class T>
+LAT_DEV m3<T> zero3() {
+    m3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r.e[i][j] = {T(0), T(0)};
+    return r;
+}
+// A * B
+template <class T>
+LAT_DEV m3<T> mul_nn(const m3<T>& a, const m3<T>& b) {
+    m3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmul(a.e[i][0], b.e[0][j]);
+            s = s + cmul(a.e[i][1], b.e[1][j]);
+            s = s + cmul(a.e[i][2], b.e[2][j]);
+            r.e[i][j] = s;
+        }
+    return r;
+}
+// A * B^dagger
+template <class T>
+LAT_DEV m3<T> mul_na(const m3<T>& a, const m3<T>& b) {
+    m3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmulj(a.e[i][0], b.e[j][0]);
+            s = s + cmulj(a.e[i][1], b.e[j][1]);
+            s = s + cmulj(a.e[i][2], b.e[j][2]);
+            r.e[i][j] = s;
+        }
+    return r;
+}
+// A^dagger * B
+template <class T>
+LAT_DEV m3<T> mul_an(const m3<T>& a, const m3<T>& b) {
+    m3<T> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cjmul(a.e[0][i], b.e[0][j]);
+            s = s + cjmul(a.e[1][i], b.e[1][j]);
+            s = s + cjmul(a.e[2][i], b.e[2][j]);
+            r.e[i][j] = s;
+        }
+    return r;
+}
+template <class T>
+LAT_DEV void acc3(m3<T>& a, const m3<T>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.e[i][j] = a.e[i][j] + b.e[i][j];
+}
+template <class T>
+LAT_DEV T re_tr(const m3<T>& a) { return a.e[0][0].re + a.e[1][1].re + a.e[2][2].re; }
+// Re Tr(A * B^dagger) without forming the product
+template <class T>
+LAT_DEV T re_tr_na(const m3<T>& a, const m3<T>& b) {
+    T s = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += a.e[i][k].re * b.e[i][k].re + a.e[i][k].im * b.e[i][k].im;
+    return s;
+}
+template <class T>
+LAT_DEV m3<T> identity3() {
+    m3<T> r = zero3<T>();
+    r.e[0][0].re = r.e[1][1].re = r.e[2][2].re = T(1);
+    return r;
+}
+template <class To, class From>
+LAT_DEV m3<To> cast3(const m3<From>& a) {
+    m3<To> r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r.e[i][j] = {To(a.e[i][j].re), To(a.e[i][j].im)};
+    return r;
+}
+// row 3 = conj(row1 x row2): completes two orthonormal rows to det = 1
+template <class T>
+LAT_DEV void third_row(m3<T>& a) {
+    a.e[2][0] = conj(cmul(a.e[0][1], a.e[1][2]) - cmul(a.e[0][2], a.e[1][1]));
+    a.e[2][1] = conj(cmul(a.e[0][2], a.e[1][0]) - cmul(a.e[0][0], a.e[1][2]));
+    a.e[2][2] = conj(cmul(a.e[0][0], a.e[1][1]) - cmul(a.e[0][1], a.e[1][0]));
+}
+// Gram-Schmidt on rows 1-2, then row 3 from the cross product (FP64)
+LAT_DEV void reunit3(m3<double>& a) {
+    double n1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) n1 += a.e[0][c].re * a.e[0][c].re + a.e[0][c].im * a.e[0][c].im;
+    n1 = 1.0 / sqrt(n1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.e[0][c] = {a.e[0][c].re * n1, a.e[0][c].im * n1};
+    cx<double> d = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d = d + cjmul(a.e[0][c], a.e[1][c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.e[1][c] = a.e[1][c] - cmul(d, a.e[0][c]);
+    double n2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) n2 += a.e[1][c].re * a.e[1][c].re + a.e[1][c].im * a.e[1][c].im;
+    n2 = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.e[1][c] = {a.e[1][c].re * n2, a.e[1][c].im * n2};
+    third_row(a);
+}
+
+// ---------------------------------------------------------------------------
+// quaternions q0 + i(q1 s1 + q2 s2 + q3 s3) for SU(2)
+// ---------------------------------------------------------------------------
+template <class T>
+struct qt {
+    T q0, q1, q2, q3;
+};
+// a * b
+template <class T>
+LAT_DEV qt<T> qmul(qt<T> a, qt<T> b) {
+    return {a.q0 * b.q0 - a.q1 * b.q1 - a.q2 * b.q2 - a.q3 * b.q3,
+            a.q0 * b.q1 + b.q0 * a.q1 - (a.q2 * b.q3 - a.q3 * b.q2),
+            a.q0 * b.q2 + b.q0 * a.q2 - (a.q3 * b.q1 - a.q1 * b.q3),
+            a.q0 * b.q3 + b.q0 * a.q3 - (a.q1 * b.q2 - a.q2 * b.q1)};
+}
+template <class T>
+LAT_DEV qt<T> qdag(qt<T> a) { return {a.q0, -a.q1, -a.q2, -a.q3}; }
+// a * b^dagger
+template <class T>
+LAT_DEV qt<T> qmul_na(qt<T> a, qt<T> b) { return qmul(a, qdag(b)); }
+template <class T>
+LAT_DEV qt<T> qadd(qt<T> a, qt<T> b) { return {a.q0 + b.q0, a.q1 + b.q1, a.q2 + b.q2, a.q3 + b.q3}; }
+template <class T>
+LAT_DEV T qnorm2(qt<T> a) { return a.q0 * a.q0 + a.q1 * a.q1 + a.q2 * a.q2 + a.q3 * a.q3; }
+
+// Left multiplication of rows a, b of a 3x3 matrix by the SU(2) element r
+// embedded in the (a,b) block: (r00 r01; r10 r11) =
+// (r0 + i r3, r2 + i r1; -r2 + i r1, r0 - i r3).
+template <class T>
+LAT_DEV void left_mul_block(m3<T>& m, int a, int b, qt<T> r) {
+    const cx<T> r00 = {r.q0, r.q3}, r01 = {r.q2, r.q1}, r10 = {-r.q2, r.q1}, r11 = {r.q0, -r.q3};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cx<T> x = m.e[a][c], y = m.e[b][c];
+        m.e[a][c] = cmul(r00, x) + cmul(r01, y);
+        m.e[b][c] = cmul(r10, x) + cmul(r11, y);
+    }
+}
+// Quaternion (SU(2) projection) of the (a,b) block of a 3x3 matrix.
+template <class T>
+LAT_DEV qt<T> block_quat(const m3<T>& m, int a, int b) {
+    return {T(0.5) * (m.e[a][a].re + m.e[b][b].re), T(0.5) * (m.e[a][b].im + m.e[b][a].im),
+            T(0.5) * (m.e[a][b].re - m.e[b][a].re), T(0.5) * (m.e[a][a].im - m.e[b][b].im)};
+}
+
+// ---------------------------------------------------------------------------
+// random streams
+// ---------------------------------------------------------------------------
+// 24 high bits, centred: exact in FP32 and FP64, never 0 or 1
+LAT_DEV double u24(uint32_t w) { return ((double)(w >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+struct u4 {
+    uint32_t x, y, z, w;
+};
+// Philox4x32-10 (Salmon et al., SC'11)
+LAT_DEV u4 philox10(u4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = {hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// MRG32k3a step on a register-resident state; returns z in [1, m1].
+struct mrg_state {
+    uint32_t s[6];
+};
+LAT_DEV uint32_t mrg_step(mrg_state& st) {
+    const uint64_t m1 = 4294967087ull, m2 = 4294944443ull;
+    // -a * x mod m == a * (m - x) mod m keeps every term non-negative (< 2^54)
+    uint64_t p1 = (1403580ull * st.s[1] + 810728ull * (m1 - st.s[0])) % m1;
+    uint64_t p2 = (527612ull * st.s[5] + 1370589ull * (m2 - st.s[3])) % m2;
+    st.s[0] = st.s[1];
+    st.s[1] = st.s[2];
+    st.s[2] = (uint32_t)p1;
+    st.s[3] = st.s[4];
+    st.s[4] = st.s[5];
+    st.s[5] = (uint32_t)p2;
+    return (uint32_t)(p1 > p2 ? p1 - p2 : p1 + m1 - p2);
+}
+
+// Uniforms of one link update.  Philox addresses slots by
+// (site, lattice, 4*h + mu, g*(NHIT+1) + t); MRG draws sequentially.
+template <int RNG>
+struct draws;
+
+template <>
+struct draws<LAT_RNG_PHILOX_I> {
+    uint32_t site, lat, word2, k0, k1;
+    int nhit;
+    LAT_DEV void try4(int g, int t, double R[4]) {
+        u4 o = philox10({site, lat, word2, (uint32_t)(g * (nhit + 1) + t)}, k0, k1);
+        R[0] = u24(o.x);
+        R[1] = u24(o.y);
+        R[2] = u24(o.z);
+        R[3] = u24(o.w);
+    }
+    LAT_DEV void dir2(int g, double D[2]) {
+        u4 o = philox10({site, lat, word2, (uint32_t)(g * (nhit + 1) + nhit)}, k0, k1);
+        D[0] = u24(o.x);
+        D[1] = u24(o.y);
+    }
+};
+template <>
+struct draws<LAT_RNG_MRG_I> {
+    mrg_state st;
+    LAT_DEV void try4(int, int, double R[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[k] = u24(mrg_step(st));
+    }
+    LAT_DEV void dir2(int, double D[2]) {
+        D[0] = u24(mrg_step(st));
+        D[1] = u24(mrg_step(st));
+    }
+};
+template <>
+struct draws<LAT_RNG_CONST_I> {
+    double c;
+    LAT_DEV void try4(int, int, double R[4]) { R[0] = R[1] = R[2] = R[3] = c; }
+    LAT_DEV void dir2(int, double D[2]) { D[0] = D[1] = c; }
+};
+
+// Kennedy-Pendleton: x0 with density sqrt(1-x0^2) exp(alpha x0).
+// Returns the accepted try or -1 (then x = 1).
+template <class DR>
+LAT_DEV int kp(double alpha, int nhit, DR& d, int g, qt<double>& x) {
+    for (int t = 0; t < nhit; ++t) {
+        double R[4];
+        d.try4(g, t, R);
+        const double c = cos(TWO_PI * R[1]);
+        const double lam2 = -(log(R[0]) + c * c * log(R[2])) / (2.0 * alpha);
+        if (R[3] * R[3] <= 1.0 - lam2) {
+            double D[2];
+            d.dir2(g, D);
+            const double s = 2.0 * sqrt(lam2 * (1.0 - lam2));
+            const double ct = 2.0 * D[0] - 1.0;
+            const double st = sqrt(1.0 - ct * ct);
+            double sp, cp;
+            sincos(TWO_PI * D[1], &sp, &cp);
+            x = {1.0 - 2.0 * lam2, s * st * cp, s * st * sp, s * ct};
+            return t;
+        }
+    }
+    x = {1.0, 0.0, 0.0, 0.0};
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// geometry of the parity-split layout
+// ---------------------------------------------------------------------------
+struct coord4 {
+    int x, y, z, t;
+};
+// half-lattice index s of parity p -> coordinates
+LAT_DEV coord4 decode(const LatGeom& g, int64_t s, int p) {
+    int64_t r = s / g.nxh;
+    const int xh = (int)(s - r * g.nxh);
+    const int64_t r2 = r / g.ny;
+    const int y = (int)(r - r2 * g.ny);
+    const int t = (int)(r2 / g.nz);
+    const int z = (int)(r2 - (int64_t)t * g.nz);
+    const int x = 2 * xh + ((p + y + z + t) & 1);
+    return {x, y, z, t};
+}
+LAT_DEV int64_t half_index(const LatGeom& g, coord4 c) {
+    return (int64_t)(c.x >> 1) + (int64_t)g.nxh * (c.y + (int64_t)g.ny * (c.z + (int64_t)g.nz * c.t));
+}
+LAT_DEV int64_t canon_index(const LatGeom& g, coord4 c) {
+    return c.x + (int64_t)g.nx * (c.y + (int64_t)g.ny * (c.z + (int64_t)g.nz * c.t));
+}
+LAT_DEV coord4 step(const LatGeom& g, coord4 c, int mu, int d) {
+    switch (mu) {
+        case 0: c.x += d; c.x = c.x < 0 ? c.x + g.nx : (c.x >= g.nx ? c.x - g.nx : c.x); break;
+        case 1: c.y += d; c.y = c.y < 0 ? c.y + g.ny : (c.y >= g.ny ? c.y - g.ny : c.y); break;
+        case 2: c.z += d; c.z = c.z < 0 ? c.z + g.nz : (c.z >= g.nz ? c.z - g.nz : c.z); break;
+        default: c.t += d; c.t = c.t < 0 ? c.t + g.nt : (c.t >= g.nt ? c.t - g.nt : c.t); break;
+    }
+    return c;
+}
+
+// Background phase theta of link (c, mu): B = exp(i theta T).
+LAT_DEV double bg_theta(const LatGeom& g, int flux, coord4 c, int mu) {
+    if (flux == 0 || mu > 1) return 0.0;
+    const double phi = TWO_PI * (double)flux / (double)(g.nx * g.ny);
+    if (mu == 1) return phi * (double)c.x;
+    if (c.x == g.nx - 1) return -phi * (double)(g.nx * c.y);
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// storage forms: each (parity, mu) holds NP planes of 8- or 16-byte vectors,
+// every plane a contiguous array over the padded half lattice.
+// ---------------------------------------------------------------------------
+struct st_f64 {  // SU(3), 18 doubles: 9 planes of (re, im)
+    using real = double;
+    using mat = m3<double>;
+    static constexpr int NP = 9;
+    static constexpr int VB = 16;
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        const double2* p = reinterpret_cast<const double2*>(base) + s;
+        mat m;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 v = p[k * plane_stride];
+            m.e[k / 3][k % 3] = {v.x, v.y};
+        }
+        return m;
+    }
+    LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
+        double2* p = reinterpret_cast<double2*>(base) + s;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) p[k * plane_stride] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+    }
+};
+struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
+    using real = float;
+    using mat = m3<float>;
+    static constexpr int NP = 9;
+    static constexpr int VB = 8;
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        const float2* p = reinterpret_cast<const float2*>(base) + s;
+        mat m;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            float2 v = p[k * plane_stride];
+            m.e[k / 3][k % 3] = {v.x, v.y};
+        }
+        return m;
+    }
+    LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
+        float2* p = reinterpret_cast<float2*>(base) + s;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) p[k * plane_stride] = make_float2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+    }
+};
+struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
+    using real = float;
+    using mat = m3<float>;
+    static constexpr int NP = 3;
+    static constexpr int VB = 16;
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        const float4* p = reinterpret_cast<const float4*>(base) + s;
+        float4 a = p[0], b = p[plane_stride], c = p[2 * plane_stride];
+        mat m;
+        m.e[0][0] = {a.x, a.y};
+        m.e[0][1] = {a.z, a.w};
+        m.e[0][2] = {b.x, b.y};
+        m.e[1][0] = {b.z, b.w};
+        m.e[1][1] = {c.x, c.y};
+        m.e[1][2] = {c.z, c.w};
+        third_row(m);
+        return m;
+    }
+    LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
+        float4* p = reinterpret_cast<float4*>(base) + s;
+        p[0] = make_float4(m.e[0][0].re, m.e[0][0].im, m.e[0][1].re, m.e[0][1].im);
+        p[plane_stride] = make_float4(m.e[0][2].re, m.e[0][2].im, m.e[1][0].re, m.e[1][0].im);
+        p[2 * plane_stride] = make_float4(m.e[1][1].re, m.e[1][1].im, m.e[1][2].re, m.e[1][2].im);
+    }
+};
+struct sq_f64 {  // SU(2), 4 doubles: 2 planes of double2
+    using real = double;
+    using mat = qt<double>;
+    static constexpr int NP = 2;
+    static constexpr int VB = 16;
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        const double2* p = reinterpret_cast<const double2*>(base) + s;
+        double2 a = p[0], b = p[plane_stride];
+        return {a.x, a.y, b.x, b.y};
+    }
+    LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
+        double2* p = reinterpret_cast<double2*>(base) + s;
+        p[0] = make_double2(m.q0, m.q1);
+        p[plane_stride] = make_double2(m.q2, m.q3);
+    }
+};
+struct sq_f32 {  // SU(2), 4 floats: 1 plane of float4
+    using real = float;
+    using mat = qt<float>;
+    static constexpr int NP = 1;
+    static constexpr int VB = 16;
+    LAT_DEV static mat load(const char* base, int64_t, int64_t s) {
+        float4 a = reinterpret_cast<const float4*>(base)[s];
+        return {a.x, a.y, a.z, a.w};
+    }
+    LAT_DEV static void store(char* base, int64_t, int64_t s, const mat& m) {
+        reinterpret_cast<float4*>(base)[s] = make_float4(m.q0, m.q1, m.q2, m.q3);
+    }
+};
+
+// Address of the first plane of (parity p, direction mu).
+template <class ST>
+LAT_DEV const char* dir_base(const char* links, int64_t vh_pad, int p, int mu) {
+    return links + (int64_t)((p * 4 + mu) * ST::NP) * vh_pad * ST::VB;
+}
+template <class ST>
+LAT_DEV typename ST::mat load_link(const char* links, int64_t vh_pad, int p, int mu, int64_t s) {
+    return ST::load(dir_base<ST>(links, vh_pad, p, mu), vh_pad, s);
+}
+
+}  // namespace latdev

@@ -1,0 +1,719 @@
+// HIP kernels for gfx950: checkerboard heat-bath / overrelaxation passes,
+// initialisation, observables and layout conversion.
+//
+// One thread updates one link U_mu(x) of the pass parity.  Links live in a
+// parity-split structure of arrays (see lat_dev.hpp), so consecutive threads
+// read consecutive 8/16-byte vectors of every plane: each of the 19 link
+// reads of a staple is a fully coalesced wave-wide load, and neighbour reuse
+// is served from L2 / Infinity Cache.  Work-groups are mapped so that each
+// XCD (own L2) sweeps a contiguous slab of the lattice.
+#include <hip/hip_runtime.h>
+
+#include "lat_dev.hpp"
+#include "lat_launch.hpp"
+
+using namespace latdev;
+
+namespace {
+
+// Block -> tile map.  The dispatcher hands block b to XCD b % 8; the
+// XCD-aware order gives every XCD one contiguous range of tiles so that the
+// y/z/t neighbours a tile reads are mostly in that XCD's own L2.
+LAT_DEV int64_t tile_index(int order) {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    if (order == 1) return b;
+    if (order == 2) return nb - 1 - b;
+    const int64_t x = b & 7, k = b >> 3;
+    const int64_t per = nb >> 3, rem = nb & 7;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+constexpr int SUB_A[3] = {0, 1, 0};
+constexpr int SUB_B[3] = {1, 2, 2};
+
+// ---------------------------------------------------------------------------
+// SU(3) pass
+// ---------------------------------------------------------------------------
+template <class ST, int KIND, bool REUNIT, int RNG>
+__global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
+    using T = typename ST::real;
+    using M = m3<T>;
+    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= a.g.vh) return;
+    const int p = a.parity, q = 1 - p, mu = a.mu;
+    const int64_t vp = a.g.vh_pad;
+    const char* L = a.links;
+    const coord4 c = decode(a.g, s, p);
+    const coord4 cpm = step(a.g, c, mu, +1);
+    const int64_t s_pm = half_index(a.g, cpm);
+
+    // staple A = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+    //                           + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)]
+    M A = zero3<T>();
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        const int64_t s_pn = half_index(a.g, step(a.g, c, nu, +1));
+        const int64_t s_mn = half_index(a.g, step(a.g, c, nu, -1));
+        const int64_t s_pmmn = half_index(a.g, step(a.g, cpm, nu, -1));
+        {
+            M t = mul_na(load_link<ST>(L, vp, q, nu, s_pm), load_link<ST>(L, vp, q, mu, s_pn));
+            acc3(A, mul_na(t, load_link<ST>(L, vp, p, nu, s)));
+        }
+        {
+            M t = mul_nn(load_link<ST>(L, vp, q, mu, s_mn), load_link<ST>(L, vp, p, nu, s_pmmn));
+            acc3(A, mul_an(t, load_link<ST>(L, vp, q, nu, s_mn)));
+        }
+    }
+
+    M U = load_link<ST>(L, vp, p, mu, s);
+    M W = mul_nn(U, A);  // link times staple: the local action is Re Tr(W)
+
+    int64_t canon = 0;
+    draws<RNG> d;
+    if constexpr (KIND == 0) {
+        canon = canon_index(a.g, c);
+        if constexpr (RNG == LAT_RNG_PHILOX_I) {
+            d.site = (uint32_t)canon;
+            d.lat = a.lat_id;
+            d.word2 = (uint32_t)(4 * (*a.hb_count + (uint64_t)a.hb_offset) + mu);
+            d.k0 = a.key0;
+            d.k1 = a.key1;
+            d.nhit = a.nhit;
+        } else if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+            for (int w = 0; w < 6; ++w) d.st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+        } else {
+            d.c = a.rng_const;
+        }
+    }
+
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const int ia = SUB_A[g], ib = SUB_B[g];
+        const qt<T> qb = block_quat(W, ia, ib);
+        const qt<double> qd = {(double)qb.q0, (double)qb.q1, (double)qb.q2, (double)qb.q3};
+        const double k = sqrt(qnorm2(qd));
+        qt<double> r;
+        if constexpr (KIND == 0) {
+            const double alpha = 2.0 * a.beta * k / 3.0;
+            int8_t* log = a.accept_log ? a.accept_log + ((((int64_t)a.hb_offset * 4 + mu) * (2 * a.g.vh) + canon) * 3 + g) : nullptr;
+            if (!(alpha >= 1e-12)) {
+                if (log) *log = -1;
+                continue;
+            }
+            qt<double> x;
+            const int t = kp(alpha, a.nhit, d, g, x);
+            if (log) *log = (int8_t)t;
+            if (t < 0) continue;
+            const double ik = 1.0 / k;
+            r = qmul_na(x, qt<double>{qd.q0 * ik, qd.q1 * ik, qd.q2 * ik, qd.q3 * ik});
+        } else {
+            if (!(k > 0.0)) continue;
+            const double ik = 1.0 / k;
+            const qt<double> vd = {qd.q0 * ik, -qd.q1 * ik, -qd.q2 * ik, -qd.q3 * ik};
+            r = qmul(vd, vd);
+        }
+        const qt<T> rt = {(T)r.q0, (T)r.q1, (T)r.q2, (T)r.q3};
+        left_mul_block(U, ia, ib, rt);
+        if (g < 2) left_mul_block(W, ia, ib, rt);
+    }
+
+    if constexpr (REUNIT) {
+        m3<double> ud = cast3<double>(U);
+        reunit3(ud);
+        U = cast3<T>(ud);
+    }
+    ST::store(const_cast<char*>(dir_base<ST>(L, vp, p, mu)), vp, s, U);
+    if constexpr (KIND == 0 && RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+        for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = d.st.s[w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SU(2) pass (quaternions)
+// ---------------------------------------------------------------------------
+template <class ST, int KIND, bool REUNIT, int RNG>
+__global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
+    using T = typename ST::real;
+    using Q = qt<T>;
+    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= a.g.vh) return;
+    const int p = a.parity, q = 1 - p, mu = a.mu;
+    const int64_t vp = a.g.vh_pad;
+    const char* L = a.links;
+    const coord4 c = decode(a.g, s, p);
+    const coord4 cpm = step(a.g, c, mu, +1);
+    const int64_t s_pm = half_index(a.g, cpm);
+
+    Q A = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        const int64_t s_pn = half_index(a.g, step(a.g, c, nu, +1));
+        const int64_t s_mn = half_index(a.g, step(a.g, c, nu, -1));
+        const int64_t s_pmmn = half_index(a.g, step(a.g, cpm, nu, -1));
+        Q f = qmul_na(qmul_na(load_link<ST>(L, vp, q, nu, s_pm), load_link<ST>(L, vp, q, mu, s_pn)),
+                      load_link<ST>(L, vp, p, nu, s));
+        A = qadd(A, f);
+        Q b = qmul(qdag(qmul(load_link<ST>(L, vp, q, mu, s_mn), load_link<ST>(L, vp, p, nu, s_pmmn))),
+                   load_link<ST>(L, vp, q, nu, s_mn));
+        A = qadd(A, b);
+    }
+    Q U = load_link<ST>(L, vp, p, mu, s);
+    const Q W = qmul(U, A);
+    const qt<double> qd = {(double)W.q0, (double)W.q1, (double)W.q2, (double)W.q3};
+    const double k = sqrt(qnorm2(qd));
+    bool apply = false;
+    qt<double> r;
+    if constexpr (KIND == 0) {
+        const int64_t canon = canon_index(a.g, c);
+        draws<RNG> d;
+        if constexpr (RNG == LAT_RNG_PHILOX_I) {
+            d.site = (uint32_t)canon;
+            d.lat = a.lat_id;
+            d.word2 = (uint32_t)(4 * (*a.hb_count + (uint64_t)a.hb_offset) + mu);
+            d.k0 = a.key0;
+            d.k1 = a.key1;
+            d.nhit = a.nhit;
+        } else if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+            for (int w = 0; w < 6; ++w) d.st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+        } else {
+            d.c = a.rng_const;
+        }
+        const double alpha = 2.0 * a.beta * k / 2.0;
+        int8_t* log = a.accept_log ? a.accept_log + ((((int64_t)a.hb_offset * 4 + mu) * (2 * a.g.vh) + canon) * 3) : nullptr;
+        if (alpha >= 1e-12) {
+            qt<double> x;
+            const int t = kp(alpha, a.nhit, d, 0, x);
+            if (log) *log = (int8_t)t;
+            if (t >= 0) {
+                const double ik = 1.0 / k;
+                r = qmul_na(x, qt<double>{qd.q0 * ik, qd.q1 * ik, qd.q2 * ik, qd.q3 * ik});
+                apply = true;
+            }
+        } else if (log) {
+            *log = -1;
+        }
+        if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+            for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = d.st.s[w];
+        }
+    } else {
+        if (k > 0.0) {
+            const double ik = 1.0 / k;
+            const qt<double> vd = {qd.q0 * ik, -qd.q1 * ik, -qd.q2 * ik, -qd.q3 * ik};
+            r = qmul(vd, vd);
+            apply = true;
+        }
+    }
+    if (apply) U = qmul(Q{(T)r.q0, (T)r.q1, (T)r.q2, (T)r.q3}, U);
+    if constexpr (REUNIT) {
+        qt<double> ud = {(double)U.q0, (double)U.q1, (double)U.q2, (double)U.q3};
+        const double in = 1.0 / sqrt(qnorm2(ud));
+        U = {(T)(ud.q0 * in), (T)(ud.q1 * in), (T)(ud.q2 * in), (T)(ud.q3 * in)};
+    }
+    ST::store(const_cast<char*>(dir_base<ST>(L, vp, p, mu)), vp, s, U);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation: cold (unit) or Haar-random links, times the background
+// ---------------------------------------------------------------------------
+LAT_DEV void box_muller(double u1, double u2, double& g1, double& g2) {
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(TWO_PI * u2, &sn, &cs);
+    g1 = r * cs;
+    g2 = r * sn;
+}
+
+template <int RNG>
+LAT_DEV void init_uniforms(const InitArgs& a, int64_t canon, int mu, int nu, double* u, mrg_state& st) {
+    if constexpr (RNG == LAT_RNG_PHILOX_I) {
+        for (int j = 0; j < nu / 4; ++j) {
+            u4 o = philox10({(uint32_t)canon, a.lat_id, 0xFFFFFFFFu, (uint32_t)(4 * mu + j)}, a.key0, a.key1);
+            u[4 * j] = u24(o.x);
+            u[4 * j + 1] = u24(o.y);
+            u[4 * j + 2] = u24(o.z);
+            u[4 * j + 3] = u24(o.w);
+        }
+    } else if constexpr (RNG == LAT_RNG_MRG_I) {
+        for (int k = 0; k < nu; ++k) u[k] = u24(mrg_step(st));
+    } else {
+        for (int k = 0; k < nu; ++k) u[k] = a.rng_const;
+    }
+}
+
+template <class ST, int RNG>
+__global__ void __launch_bounds__(256) su3_init(InitArgs a) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (s >= a.g.vh) return;
+    const int64_t vp = a.g.vh_pad;
+    const coord4 c = decode(a.g, s, p);
+    const int64_t canon = canon_index(a.g, c);
+    mrg_state st;
+    if constexpr (RNG == LAT_RNG_MRG_I) {
+        for (int w = 0; w < 6; ++w) st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        m3<double> U = identity3<double>();
+        if (a.start == 1) {
+            double u[12];
+            init_uniforms<RNG>(a, canon, mu, 12, u, st);
+#pragma unroll
+            for (int row = 0; row < 2; ++row)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    double re, im;
+                    box_muller(u[6 * row + 2 * cc], u[6 * row + 2 * cc + 1], re, im);
+                    U.e[row][cc] = {re, im};
+                }
+            reunit3(U);
+        }
+        const double th = bg_theta(a.g, a.flux, c, mu);
+        if (th != 0.0) {
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const cx<double> e = {cs, sn}, ec = {cs, -sn};
+            for (int r = 0; r < 3; ++r) {
+                U.e[r][0] = cmul(U.e[r][0], e);
+                U.e[r][1] = cmul(U.e[r][1], ec);
+            }
+        }
+        ST::store(const_cast<char*>(dir_base<ST>(a.links, vp, p, mu)), vp, s, cast3<typename ST::real>(U));
+    }
+    if constexpr (RNG == LAT_RNG_MRG_I) {
+        for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = st.s[w];
+    }
+}
+
+template <class ST, int RNG>
+__global__ void __launch_bounds__(256) su2_init(InitArgs a) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (s >= a.g.vh) return;
+    const int64_t vp = a.g.vh_pad;
+    const coord4 c = decode(a.g, s, p);
+    const int64_t canon = canon_index(a.g, c);
+    mrg_state st;
+    if constexpr (RNG == LAT_RNG_MRG_I) {
+        for (int w = 0; w < 6; ++w) st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        qt<double> U = {1.0, 0.0, 0.0, 0.0};
+        if (a.start == 1) {
+            double u[4], g[4];
+            init_uniforms<RNG>(a, canon, mu, 4, u, st);
+            box_muller(u[0], u[1], g[0], g[1]);
+            box_muller(u[2], u[3], g[2], g[3]);
+            const double nn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3]);
+            U = {g[0] / nn, g[1] / nn, g[2] / nn, g[3] / nn};
+        }
+        const double th = bg_theta(a.g, a.flux, c, mu);
+        if (th != 0.0) {
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            U = qmul(U, qt<double>{cs, 0.0, 0.0, sn});
+        }
+        using T = typename ST::real;
+        ST::store(const_cast<char*>(dir_base<ST>(a.links, vp, p, mu)), vp, s, qt<T>{(T)U.q0, (T)U.q1, (T)U.q2, (T)U.q3});
+    }
+    if constexpr (RNG == LAT_RNG_MRG_I) {
+        for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = st.s[w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// observables: per-block FP64 partials (wave shuffle, then LDS across the
+// 4 waves of a block), then one block folds the partials with Neumaier
+// compensation in a fixed order.
+// ---------------------------------------------------------------------------
+template <int NV>
+LAT_DEV void block_reduce_store(double (&v)[NV], double* out, int64_t stride, int64_t slot) {
+    __shared__ double sh[NV][4];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        v[k] = x;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k][wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double x = 0.0;
+            for (int w = 0; w < nw; ++w) x += sh[k][w];
+            out[k * stride + slot] = x;
+        }
+    }
+}
+
+template <class ST>
+__global__ void __launch_bounds__(256) su3_plaq(MeasArgs a) {
+    using T = typename ST::real;
+    using M = m3<T>;
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int p = blockIdx.y, q = 1 - p;
+    double v[2] = {0.0, 0.0};
+    if (s < a.g.vh) {
+        const int64_t vp = a.g.vh_pad;
+        const coord4 c = decode(a.g, s, p);
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            const int64_t s_pm = half_index(a.g, step(a.g, c, mu, +1));
+            const M umu = load_link<ST>(a.links, vp, p, mu, s);
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const int64_t s_pn = half_index(a.g, step(a.g, c, nu, +1));
+                // Re Tr[(U_mu(x) U_nu(x+mu)) (U_nu(x) U_mu(x+nu))^+]
+                const M left = mul_nn(umu, load_link<ST>(a.links, vp, q, nu, s_pm));
+                const M right = mul_nn(load_link<ST>(a.links, vp, p, nu, s), load_link<ST>(a.links, vp, q, mu, s_pn));
+                const double tr = (double)re_tr_na(left, right) * (1.0 / 3.0);
+                v[nu == 3 ? 1 : 0] += tr;
+            }
+        }
+    }
+    block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + blockIdx.x);
+}
+
+template <class ST>
+__global__ void __launch_bounds__(256) su2_plaq(MeasArgs a) {
+    using T = typename ST::real;
+    using Q = qt<T>;
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int p = blockIdx.y, q = 1 - p;
+    double v[2] = {0.0, 0.0};
+    if (s < a.g.vh) {
+        const int64_t vp = a.g.vh_pad;
+        const coord4 c = decode(a.g, s, p);
+#pragma unroll
+        for (int mu = 0; mu < 3; ++mu) {
+            const int64_t s_pm = half_index(a.g, step(a.g, c, mu, +1));
+            const Q umu = load_link<ST>(a.links, vp, p, mu, s);
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const int64_t s_pn = half_index(a.g, step(a.g, c, nu, +1));
+                const Q left = qmul(umu, load_link<ST>(a.links, vp, q, nu, s_pm));
+                const Q right = qmul(load_link<ST>(a.links, vp, p, nu, s), load_link<ST>(a.links, vp, q, mu, s_pn));
+                // (1/2) Re Tr(left right^+) = scalar part of left * right^dagger
+                const double tr = (double)(left.q0 * right.q0 + left.q1 * right.q1 + left.q2 * right.q2 + left.q3 * right.q3);
+                v[nu == 3 ? 1 : 0] += tr;
+            }
+        }
+    }
+    block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + blockIdx.x);
+}
+
+template <class ST>
+__global__ void __launch_bounds__(256) su3_poly(MeasArgs a) {
+    using T = typename ST::real;
+    const int64_t xs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t vs = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+    double v[2] = {0.0, 0.0};
+    if (xs < vs) {
+        const int x = (int)(xs % a.g.nx);
+        const int y = (int)((xs / a.g.nx) % a.g.ny);
+        const int z = (int)(xs / ((int64_t)a.g.nx * a.g.ny));
+        m3<T> P = identity3<T>();
+        for (int t = 0; t < a.g.nt; ++t) {
+            const coord4 c = {x, y, z, t};
+            const int par = (x + y + z + t) & 1;
+            P = mul_nn(P, load_link<ST>(a.links, a.g.vh_pad, par, 3, half_index(a.g, c)));
+        }
+        v[0] = ((double)P.e[0][0].re + (double)P.e[1][1].re + (double)P.e[2][2].re) * (1.0 / 3.0);
+        v[1] = ((double)P.e[0][0].im + (double)P.e[1][1].im + (double)P.e[2][2].im) * (1.0 / 3.0);
+    }
+    block_reduce_store<2>(v, a.partial + 4 * (int64_t)a.nb_plaq, a.nb_poly, blockIdx.x);
+}
+
+template <class ST>
+__global__ void __launch_bounds__(256) su2_poly(MeasArgs a) {
+    using T = typename ST::real;
+    const int64_t xs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t vs = (int64_t)a.g.nx * a.g.ny * a.g.nz;
+    double v[2] = {0.0, 0.0};
+    if (xs < vs) {
+        const int x = (int)(xs % a.g.nx);
+        const int y = (int)((xs / a.g.nx) % a.g.ny);
+        const int z = (int)(xs / ((int64_t)a.g.nx * a.g.ny));
+        qt<T> P = {T(1), T(0), T(0), T(0)};
+        for (int t = 0; t < a.g.nt; ++t) {
+            const coord4 c = {x, y, z, t};
+            const int par = (x + y + z + t) & 1;
+            P = qmul(P, load_link<ST>(a.links, a.g.vh_pad, par, 3, half_index(a.g, c)));
+        }
+        v[0] = (double)P.q0;  // (1/2) Tr of an SU(2) element is real
+        v[1] = 0.0;
+    }
+    block_reduce_store<2>(v, a.partial + 4 * (int64_t)a.nb_plaq, a.nb_poly, blockIdx.x);
+}
+
+// Neumaier-compensated fold of the partials in a fixed order.
+struct nsum {
+    double s, c;
+};
+LAT_DEV nsum nadd(nsum a, double x) {
+    const double t = a.s + x;
+    a.c += (fabs(a.s) >= fabs(x)) ? (a.s - t) + x : (x - t) + a.s;
+    a.s = t;
+    return a;
+}
+LAT_DEV nsum nmerge(nsum a, nsum b) {
+    a = nadd(a, b.s);
+    a.c += b.c;
+    return a;
+}
+
+__global__ void __launch_bounds__(256) meas_final(MeasArgs a, double* out, uint32_t* slot_counter) {
+    __shared__ nsum sh[4][256];
+    const int tid = threadIdx.x;
+    const int64_t n[4] = {2 * (int64_t)a.nb_plaq, 2 * (int64_t)a.nb_plaq, a.nb_poly, a.nb_poly};
+    const double* src[4] = {a.partial, a.partial + 2 * (int64_t)a.nb_plaq, a.partial + 4 * (int64_t)a.nb_plaq,
+                            a.partial + 4 * (int64_t)a.nb_plaq + a.nb_poly};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t i = tid; i < n[k]; i += 256) acc = nadd(acc, src[k][i]);
+        sh[k][tid] = acc;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sh[k][tid] = nmerge(sh[k][tid], sh[k][tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double V = 2.0 * (double)a.g.vh;
+        const double vs = (double)a.g.nx * a.g.ny * a.g.nz;
+        const double ps = (sh[0][0].s + sh[0][0].c) / (3.0 * V);
+        const double pt = (sh[1][0].s + sh[1][0].c) / (3.0 * V);
+        uint32_t slot = 0;
+        if (slot_counter) slot = *slot_counter;
+        double* o = out + 5 * (int64_t)slot;
+        o[0] = 0.5 * (ps + pt);
+        o[1] = ps;
+        o[2] = pt;
+        o[3] = (sh[2][0].s + sh[2][0].c) / vs;
+        o[4] = (sh[3][0].s + sh[3][0].c) / vs;
+        if (slot_counter) *slot_counter = slot + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// canonical FP64 <-> device layout
+// ---------------------------------------------------------------------------
+template <class ST, int NG>
+__global__ void __launch_bounds__(256) to_device(LatGeom g, const double* canon, char* links) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (s >= g.vh) return;
+    const int64_t i = canon_index(g, decode(g, s, p));
+    using T = typename ST::real;
+    for (int mu = 0; mu < 4; ++mu) {
+        char* base = const_cast<char*>(dir_base<ST>(links, g.vh_pad, p, mu));
+        if constexpr (NG == 3) {
+            const double* src = canon + (i * 4 + mu) * 18;
+            m3<T> m;
+            for (int k = 0; k < 9; ++k) m.e[k / 3][k % 3] = {(T)src[2 * k], (T)src[2 * k + 1]};
+            ST::store(base, g.vh_pad, s, m);
+        } else {
+            const double* src = canon + (i * 4 + mu) * 4;
+            ST::store(base, g.vh_pad, s, qt<T>{(T)src[0], (T)src[1], (T)src[2], (T)src[3]});
+        }
+    }
+}
+
+template <class ST, int NG>
+__global__ void __launch_bounds__(256) to_canonical(LatGeom g, const char* links, double* canon) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (s >= g.vh) return;
+    const int64_t i = canon_index(g, decode(g, s, p));
+    for (int mu = 0; mu < 4; ++mu) {
+        const typename ST::mat m = load_link<ST>(links, g.vh_pad, p, mu, s);
+        if constexpr (NG == 3) {
+            double* dst = canon + (i * 4 + mu) * 18;
+            for (int k = 0; k < 9; ++k) {
+                dst[2 * k] = (double)m.e[k / 3][k % 3].re;
+                dst[2 * k + 1] = (double)m.e[k / 3][k % 3].im;
+            }
+        } else {
+            double* dst = canon + (i * 4 + mu) * 4;
+            dst[0] = (double)m.q0;
+            dst[1] = (double)m.q1;
+            dst[2] = (double)m.q2;
+            dst[3] = (double)m.q3;
+        }
+    }
+}
+
+__global__ void bump_counter(uint64_t* c, int n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c += (uint64_t)n;
+}
+
+__global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u4 o = philox10({ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]}, k0, k1);
+    out[4 * i] = o.x;
+    out[4 * i + 1] = o.y;
+    out[4 * i + 2] = o.z;
+    out[4 * i + 3] = o.w;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+template <class ST, int KIND, bool RE, int RNG>
+hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
+    const unsigned nb = (unsigned)((a.g.vh + block - 1) / block);
+    hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), 0, st, a);
+    return hipGetLastError();
+}
+template <class ST, int KIND, bool RE, int RNG>
+hipError_t launch_su2(const PassArgs& a, int block, hipStream_t st) {
+    const unsigned nb = (unsigned)((a.g.vh + block - 1) / block);
+    hipLaunchKernelGGL((su2_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class ST, bool SU3, int K, bool R, int G>
+hipError_t launch_one(const PassArgs& a, int block, hipStream_t st) {
+    if constexpr (SU3) return launch_su3<ST, K, R, G>(a, block, st);
+    else return launch_su2<ST, K, R, G>(a, block, st);
+}
+
+template <class ST, bool SU3>
+hipError_t pass_dispatch(int kind, bool reunit, int rng, const PassArgs& a, int block, hipStream_t st) {
+    if (kind == 1)
+        return reunit ? launch_one<ST, SU3, 1, true, LAT_RNG_CONST_I>(a, block, st)
+                      : launch_one<ST, SU3, 1, false, LAT_RNG_CONST_I>(a, block, st);
+    switch (rng) {
+        case LAT_RNG_MRG_I:
+            return reunit ? launch_one<ST, SU3, 0, true, LAT_RNG_MRG_I>(a, block, st)
+                          : launch_one<ST, SU3, 0, false, LAT_RNG_MRG_I>(a, block, st);
+        case LAT_RNG_PHILOX_I:
+            return reunit ? launch_one<ST, SU3, 0, true, LAT_RNG_PHILOX_I>(a, block, st)
+                          : launch_one<ST, SU3, 0, false, LAT_RNG_PHILOX_I>(a, block, st);
+        default:
+            return reunit ? launch_one<ST, SU3, 0, true, LAT_RNG_CONST_I>(a, block, st)
+                          : launch_one<ST, SU3, 0, false, LAT_RNG_CONST_I>(a, block, st);
+    }
+}
+
+}  // namespace
+
+hipError_t lat_launch_pass(int group, int storage, int kind, bool reunit, int rng, const PassArgs& a, int block,
+                           hipStream_t st) {
+    if (group == 3) {
+        switch (storage) {
+            case LAT_ST_F64: return pass_dispatch<st_f64, true>(kind, reunit, rng, a, block, st);
+            case LAT_ST_F32: return pass_dispatch<st_f32, true>(kind, reunit, rng, a, block, st);
+            default: return pass_dispatch<st_f32c12, true>(kind, reunit, rng, a, block, st);
+        }
+    }
+    if (storage == LAT_ST_F64) return pass_dispatch<sq_f64, false>(kind, reunit, rng, a, block, st);
+    return pass_dispatch<sq_f32, false>(kind, reunit, rng, a, block, st);
+}
+
+template <class ST, bool SU3>
+static hipError_t init_dispatch(int rng, const InitArgs& a, hipStream_t st) {
+    dim3 grid((unsigned)((a.g.vh + 255) / 256), 2);
+    switch (rng) {
+        case LAT_RNG_MRG_I:
+            if constexpr (SU3) hipLaunchKernelGGL((su3_init<ST, LAT_RNG_MRG_I>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((su2_init<ST, LAT_RNG_MRG_I>), grid, dim3(256), 0, st, a);
+            break;
+        case LAT_RNG_PHILOX_I:
+            if constexpr (SU3) hipLaunchKernelGGL((su3_init<ST, LAT_RNG_PHILOX_I>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((su2_init<ST, LAT_RNG_PHILOX_I>), grid, dim3(256), 0, st, a);
+            break;
+        default:
+            if constexpr (SU3) hipLaunchKernelGGL((su3_init<ST, LAT_RNG_CONST_I>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((su2_init<ST, LAT_RNG_CONST_I>), grid, dim3(256), 0, st, a);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t lat_launch_init(int group, int storage, int rng, const InitArgs& a, hipStream_t st) {
+    if (group == 3) {
+        switch (storage) {
+            case LAT_ST_F64: return init_dispatch<st_f64, true>(rng, a, st);
+            case LAT_ST_F32: return init_dispatch<st_f32, true>(rng, a, st);
+            default: return init_dispatch<st_f32c12, true>(rng, a, st);
+        }
+    }
+    if (storage == LAT_ST_F64) return init_dispatch<sq_f64, false>(rng, a, st);
+    return init_dispatch<sq_f32, false>(rng, a, st);
+}
+
+template <class ST, bool SU3>
+static hipError_t meas_dispatch(const MeasArgs& a, double* out, uint32_t* slot, hipStream_t st) {
+    dim3 gp((unsigned)a.nb_plaq, 2);
+    dim3 gl((unsigned)a.nb_poly);
+    if constexpr (SU3) {
+        hipLaunchKernelGGL((su3_plaq<ST>), gp, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((su3_poly<ST>), gl, dim3(256), 0, st, a);
+    } else {
+        hipLaunchKernelGGL((su2_plaq<ST>), gp, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((su2_poly<ST>), gl, dim3(256), 0, st, a);
+    }
+    hipLaunchKernelGGL(meas_final, dim3(1), dim3(256), 0, st, a, out, slot);
+    return hipGetLastError();
+}
+
+hipError_t lat_launch_measure(int group, int storage, const MeasArgs& a, double* out, uint32_t* slot_counter,
+                              hipStream_t st) {
+    if (group == 3) {
+        switch (storage) {
+            case LAT_ST_F64: return meas_dispatch<st_f64, true>(a, out, slot_counter, st);
+            case LAT_ST_F32: return meas_dispatch<st_f32, true>(a, out, slot_counter, st);
+            default: return meas_dispatch<st_f32c12, true>(a, out, slot_counter, st);
+        }
+    }
+    if (storage == LAT_ST_F64) return meas_dispatch<sq_f64, false>(a, out, slot_counter, st);
+    return meas_dispatch<sq_f32, false>(a, out, slot_counter, st);
+}
+
+template <class ST, int NG>
+static hipError_t conv_dispatch(bool to_dev, const LatGeom& g, double* canon, char* links, hipStream_t st) {
+    dim3 grid((unsigned)((g.vh + 255) / 256), 2);
+    if (to_dev) hipLaunchKernelGGL((to_device<ST, NG>), grid, dim3(256), 0, st, g, canon, links);
+    else hipLaunchKernelGGL((to_canonical<ST, NG>), grid, dim3(256), 0, st, g, links, canon);
+    return hipGetLastError();
+}
+
+hipError_t lat_launch_convert(int group, int storage, bool to_dev, const LatGeom& g, double* canon, char* links,
+                              hipStream_t st) {
+    if (group == 3) {
+        switch (storage) {
+            case LAT_ST_F64: return conv_dispatch<st_f64, 3>(to_dev, g, canon, links, st);
+            case LAT_ST_F32: return conv_dispatch<st_f32, 3>(to_dev, g, canon, links, st);
+            default: return conv_dispatch<st_f32c12, 3>(to_dev, g, canon, links, st);
+        }
+    }
+    if (storage == LAT_ST_F64) return conv_dispatch<sq_f64, 2>(to_dev, g, canon, links, st);
+    return conv_dispatch<sq_f32, 2>(to_dev, g, canon, links, st);
+}
+
+hipError_t lat_launch_bump(uint64_t* counter, int n, hipStream_t st) {
+    hipLaunchKernelGGL(bump_counter, dim3(1), dim3(64), 0, st, counter, n);
+    return hipGetLastError();
+}
+
+hipError_t lat_launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, k0, k1, out, n);
+    return hipGetLastError();
+}

@@ -1,0 +1,56 @@
+// Plain structures shared by the host runtime and the kernels.
+#pragma once
+#include <stdint.h>
+
+#define LAT_RNG_MRG_I 0
+#define LAT_RNG_PHILOX_I 1
+#define LAT_RNG_CONST_I 2
+
+#define LAT_ST_F64 0
+#define LAT_ST_F32 1
+#define LAT_ST_F32C12 2
+
+struct LatGeom {
+    int nx, ny, nz, nt;
+    int nxh;         // nx / 2
+    int64_t vh;      // sites per parity
+    int64_t vh_pad;  // plane length (vh rounded up)
+};
+
+// Everything one checkerboard pass needs.
+struct PassArgs {
+    LatGeom g;
+    char* links;           // parity-split SoA link planes
+    uint32_t* mrg;         // [parity][word 0..5][vh_pad] MRG32k3a states, or null
+    const uint64_t* hb_count;  // device counter: heat-bath sweeps completed
+    int8_t* accept_log;    // [k][mu][canonical site][3] or null
+    double beta;
+    double rng_const;
+    uint32_t key0, key1, lat_id;
+    int nhit;
+    int group;
+    int mu, parity;
+    int hb_offset;         // index of this heat-bath sweep within the compound sweep
+    int tile_order;        // 0 XCD-aware, 1 identity, 2 reversed
+    int flux;
+};
+
+// Initialisation of one lattice.
+struct InitArgs {
+    LatGeom g;
+    char* links;
+    uint32_t* mrg;
+    double rng_const;
+    uint32_t key0, key1, lat_id;
+    int start;  // 0 cold, 1 hot
+    int flux;
+};
+
+// Reductions.
+struct MeasArgs {
+    LatGeom g;
+    const char* links;
+    double* partial;      // [4][nblocks]: P_s sums, P_t sums, Re L, Im L
+    int nb_plaq;          // blocks of the plaquette kernel
+    int nb_poly;          // blocks of the Polyakov kernel
+};

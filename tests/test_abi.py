@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lat.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lat_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("lat_create", "lat_sweep", "lat_measure", "lat_run", "lat_get_links", "lat_set_links",
+                 "lat_save", "lat_load", "lat_destroy", "lat_last_error", "lat_batch_create",
+                 "lat_batch_run", "lat_batch_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1310_7087_amd as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_options():
+    import paper_1310_7087_amd as P
+    o = P.default_options()
+    assert (o.storage, o.rng, o.start, o.nhit, o.seed) == (P.F64, P.RNG_PHILOX, P.HOT, 10, 0)
+    assert o.rng_const == 0.5 and o.stream is None and o.device_buffer is None
+
+
+def test_device_bytes_layout():
+    import paper_1310_7087_amd as P
+    # 32^3 x 8 SU(3): links are 4 V * (144 | 72 | 48) bytes plus small scratch
+    V = 32 ** 3 * 8
+    for st, b in ((P.F64, 144), (P.F32, 72), (P.F32_C12, 48)):
+        n = P.device_bytes(3, (32, 32, 32, 8), storage=st)
+        assert 4 * V * b <= n < 4 * V * b + (1 << 20)
+    # MRG state adds 24 bytes per site
+    a = P.device_bytes(2, (4, 4, 4, 4), rng=P.RNG_PHILOX)
+    b = P.device_bytes(2, (4, 4, 4, 4), rng=P.RNG_MRG32K3A)
+    assert b - a >= 24 * 256
+    assert P.device_bytes(3, (3, 4, 4, 4)) == 0
+    assert P.device_bytes(2, (4, 4, 4, 4), storage=P.F32_C12) == 0
+
+
+@pytest.mark.parametrize("group,dims,beta,kw,code", [
+    (3, (3, 4, 4, 4), 5.7, {}, -1),
+    (3, (4, 4, 4, 0), 5.7, {}, -1),
+    (4, (4, 4, 4, 4), 5.7, {}, -1),
+    (3, (4, 4, 4, 4), -1.0, {}, -1),
+    (3, (4, 4, 4, 4), float("nan"), {}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"nhit": 0}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"nhit": 128}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"rng": 7}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"rng": 2, "rng_const": 1.0}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"block_size": 100}, -1),
+    (2, (4, 4, 4, 4), 2.3, {"storage": 2}, -7),
+    (2, (4, 4, 4, 4), 2.3, {"rng": 0, "seed": 4294944443}, -1),
+])
+def test_create_rejects_bad_arguments_without_a_device(group, dims, beta, kw, code):
+    import paper_1310_7087_amd as P
+    with pytest.raises(P.LatError) as e:
+        P.Lattice(group, dims, beta, **kw)
+    assert e.value.code == code
+    assert P.lib.lat_last_error().decode()
+
+
+def test_null_handles_are_errors_or_noops():
+    import paper_1310_7087_amd as P
+    assert P.lib.lat_destroy(None) == 0
+    assert P.lib.lat_batch_destroy(None) == 0
+    assert P.lib.lat_sweep(None, 1, 0) == -1
+    assert P.lib.lat_measure(None, None, None) == -1
+
+
+def test_load_rejects_missing_and_corrupt_files(tmp_path):
+    import paper_1310_7087_amd as P
+    h = ctypes.c_void_p()
+    assert P.lib.lat_load(ctypes.byref(h), str(tmp_path / "none").encode(), None) == P.EIO
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(b"NOTACKPT" + b"\0" * 200)
+    assert P.lib.lat_load(ctypes.byref(h), str(bad).encode(), None) == P.ECORRUPT

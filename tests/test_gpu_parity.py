@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Tolerances: FP64 links and observables after a sweep agree to 1e-12 (max
+abs over all link components); FP32 forms to 2e-5; integer data (generator
+states, accept decisions, raw Philox words) bit-exactly."""
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import det_error, to_matrices, unitarity_error
+from inputs import SU2_4x4, SU3_16x4, su3_32x8
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1310_7087_amd")
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def pair(group, dims, beta, flux=0, rng=O.RNG_PHILOX, seed=1, start=O.HOT, storage=0, nhit=10,
+         rng_const=0.5, lattice_id=0, **kw):
+    g = P.Lattice(group, dims, beta, flux, storage=storage, rng=rng, seed=seed, start=start, nhit=nhit,
+                  rng_const=rng_const, lattice_id=lattice_id, **kw)
+    o = O.Lattice(group, dims, beta, flux=flux, rng=rng, seed=seed, start=start, nhit=nhit,
+                  rng_const=rng_const, lattice_id=lattice_id)
+    return g, o
+
+
+def maxdiff(a, b):
+    return float(np.abs(a - b).max())
+
+
+def test_philox_words_bit_exact():
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = [0x1234567, 0x89ABCDEF]
+    got = P.philox4x32_10(ctr, key)
+    want = np.array([O.philox4x32_10(c, key) for c in ctr[:512]])
+    assert np.array_equal(got[:512], want)
+
+
+@pytest.mark.parametrize("group,rng,start,flux", [
+    (3, O.RNG_PHILOX, O.HOT, 0), (3, O.RNG_MRG32K3A, O.HOT, 2), (2, O.RNG_PHILOX, O.HOT, 1),
+    (2, O.RNG_MRG32K3A, O.HOT, 0), (3, O.RNG_PHILOX, O.COLD, 3), (2, O.RNG_CONST, O.HOT, 0)])
+def test_initial_links(group, rng, start, flux):
+    g, o = pair(group, (6, 4, 4, 2), 5.0, flux=flux, rng=rng, seed=9, start=start)
+    assert maxdiff(g.get_links(), o.get_links()) < 1e-13
+    if rng == O.RNG_MRG32K3A:
+        assert np.array_equal(g.rng_state(), o.mrg_states())
+
+
+def test_su2_4x4_cold_mrg_ten_sweeps():
+    """SU(2) 4^4, beta 2.3, cold start, MRG32k3a seed 1: ten heat-bath sweeps,
+    plaquette after each; generator states bit-exact, links to 1e-12."""
+    w = SU2_4x4
+    g, o = pair(w.group, w.dims, w.beta, rng=O.RNG_MRG32K3A, seed=w.seed, start=O.COLD)
+    for k in range(w.sweeps):
+        g.sweep(1, 0)
+        o.sweep(1, 0)
+        assert np.array_equal(g.rng_state(), o.mrg_states()), k
+        assert maxdiff(g.get_links(), o.get_links()) < TOL64, k
+        pg, _ = g.measure()
+        po, _ = o.measure()
+        assert maxdiff(pg, po) < TOL64, k
+
+
+def test_su3_16x4_hot_compound_sweeps():
+    """SU(3) 16^3x4, beta 5.69, Haar start seed 7: (1 HB + 4 OR) sweeps."""
+    w = SU3_16x4
+    g, o = pair(w.group, w.dims, w.beta, seed=w.seed, start=O.HOT)
+    g.set_accept_log(True)
+    o.enable_accept_log(True)
+    for k in range(3):
+        g.sweep(w.n_hb, w.n_or)
+        o.sweep(w.n_hb, w.n_or)
+        assert np.array_equal(g.accept_log(), o.accept_log()), k
+        assert maxdiff(g.get_links(), o.get_links()) < TOL64, k
+        pg, lg = g.measure()
+        po, lo = o.measure()
+        assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
+    assert g.info()["hb_sweeps"] == o.hb_sweeps() == 3
+
+
+@pytest.mark.parametrize("group,dims", [
+    (3, (2, 2, 2, 2)), (2, (2, 2, 2, 2)), (3, (6, 4, 10, 2)), (2, (18, 6, 4, 4)), (3, (4, 2, 2, 16)),
+    (3, (34, 2, 2, 2))])
+def test_ragged_and_degenerate_shapes(group, dims):
+    # extents of 2 (x+1 = x-1), plane lengths that are not work-group multiples
+    g, o = pair(group, dims, 5.5 if group == 3 else 2.2, seed=21)
+    for _ in range(2):
+        g.sweep(1, 1)
+        o.sweep(1, 1)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
+
+
+@pytest.mark.parametrize("n", [1, 4])
+def test_flux_w_frame_matches_u_frame_oracle(n):
+    g, o = pair(3, (8, 8, 4, 4), 5.9, flux=n, seed=3, start=O.COLD)
+    pg, _ = g.measure()
+    po, _ = o.measure()
+    assert maxdiff(pg, po) < 1e-14
+    g.sweep(1, 4)
+    o.sweep(1, 4)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    assert maxdiff(g.measure()[0], o.measure()[0]) < TOL64
+
+
+def test_constant_generator_and_zero_coupling():
+    g, o = pair(2, (4, 4, 4, 4), 2.3, rng=O.RNG_CONST, start=O.COLD)
+    g.sweep(1, 0)
+    o.sweep(1, 0)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    # beta = 0: alpha below threshold, heat bath leaves links; OR with a staple still reflects
+    g, o = pair(3, (4, 4, 4, 2), 0.0, seed=4)
+    g.sweep(2, 1)
+    o.sweep(2, 1)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+
+
+def test_set_links_then_sweep_matches():
+    o = O.Lattice(3, (8, 4, 4, 4), 6.0, seed=12, start=O.HOT)
+    o.sweep(2, 2)
+    links = o.get_links()
+    g = P.Lattice(3, (8, 4, 4, 4), 6.0, seed=12, start=P.COLD)
+    g.set_links(links)
+    assert maxdiff(g.get_links(), links) == 0.0
+    # continue both from the same links and the same heat-bath counter
+    o2 = O.Lattice(3, (8, 4, 4, 4), 6.0, seed=12, start=O.COLD)
+    o2.set_links(links)
+    g.sweep(1, 1)
+    o2.sweep(1, 1)
+    assert maxdiff(g.get_links(), o2.get_links()) < TOL64
+
+
+def test_measure_random_configuration():
+    o = O.Lattice(3, (6, 6, 4, 8), 5.7, flux=2, seed=31, start=O.HOT)
+    o.sweep(1, 1)
+    g = P.Lattice(3, (6, 6, 4, 8), 5.7, flux=2, seed=31, start=P.COLD)
+    g.set_links(o.get_links())
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < 1e-14 and maxdiff(lg, lo) < 1e-14
+
+
+def test_unitarity_after_many_sweeps():
+    g = P.Lattice(3, (8, 8, 8, 4), 5.69, seed=7)
+    g.run(20, 1, 4, measure_every=0)
+    m = to_matrices(g.get_links(), 3)
+    assert unitarity_error(m) < 1e-13 and det_error(m) < 1e-13
+
+
+def test_tile_order_independence_and_repeatability():
+    res = []
+    for order in (0, 1, 2, 0):
+        g = P.Lattice(3, (8, 8, 8, 8), 5.9, seed=17, tile_order=order)
+        g.sweep(1, 2)
+        res.append(g.get_links())
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_block_size_independence(block):
+    ref = P.Lattice(3, (8, 4, 8, 4), 5.9, seed=2)
+    g = P.Lattice(3, (8, 4, 8, 4), 5.9, seed=2, block_size=block)
+    ref.sweep(1, 1)
+    g.sweep(1, 1)
+    assert np.array_equal(ref.get_links(), g.get_links())
+
+
+def test_run_series_matches_individual_measurements():
+    a = P.Lattice(3, (8, 8, 4, 4), 5.7, seed=8)
+    b = P.Lattice(3, (8, 8, 4, 4), 5.7, seed=8)
+    ps, ls = a.run(6, 1, 2, measure_every=2)
+    assert ps.shape == (3, 3)
+    for k in range(3):
+        b.sweep(1, 2)
+        b.sweep(1, 2)
+        p, l = b.measure()
+        assert np.array_equal(ps[k], p) and np.array_equal(ls[k], l)
+
+
+def test_checkpoint_round_trip(tmp_path):
+    for rng in (P.RNG_PHILOX, P.RNG_MRG32K3A):
+        a = P.Lattice(3, (4, 4, 4, 4), 5.7, seed=5, rng=rng)
+        a.sweep(1, 1)
+        path = tmp_path / f"c{rng}.ckpt"
+        a.save(str(path))
+        a.sweep(2, 1)
+        b = P.load_lattice(str(path), 3, (4, 4, 4, 4))
+        b.sweep(2, 1)
+        assert np.array_equal(a.get_links(), b.get_links())
+        assert b.info()["hb_sweeps"] == a.info()["hb_sweeps"]
+        raw = bytearray(path.read_bytes())
+        raw[200] ^= 0xFF
+        path.write_bytes(bytes(raw))
+        with pytest.raises(P.LatError):
+            P.load_lattice(str(path), 3, (4, 4, 4, 4))
+
+
+@pytest.mark.parametrize("storage,tol", [(P.F32, TOL32), (P.F32_C12, TOL32)])
+def test_fp32_forms_one_sweep(storage, tol):
+    """FP32 storage and staple arithmetic against the FP64 oracle, from the
+    same links: accept decisions (FP64 on both sides) are compared first."""
+    o = O.Lattice(3, (16, 16, 16, 4), 5.69, seed=7, start=O.HOT)
+    o.sweep(1, 2)
+    links = o.get_links()
+    g = P.Lattice(3, (16, 16, 16, 4), 5.69, seed=7, start=P.COLD, storage=storage)
+    g.set_links(links)
+    g32 = g.get_links()
+    assert maxdiff(g32, links) < 1e-6
+    o2 = O.Lattice(3, (16, 16, 16, 4), 5.69, seed=7, start=O.COLD)
+    o2.set_links(g32)  # identical starting links (already rounded to FP32)
+    g.set_accept_log(True)
+    o2.enable_accept_log(True)
+    g.sweep(1, 0)
+    o2.sweep(1, 0)
+    flips = int((g.accept_log() != o2.accept_log()).sum())
+    d = np.abs(g.get_links() - o2.get_links()).max(axis=(1, 2))
+    if flips == 0:
+        assert d.max() < tol
+    else:  # a flipped decision moves links in its light cone by O(1); it must stay rare
+        assert flips <= 2 and (d > tol).mean() < 0.01
+
+
+@pytest.mark.parametrize("storage", [P.F32, P.F32_C12])
+def test_fp32_forms_observables(storage):
+    o = O.Lattice(3, (8, 8, 8, 4), 5.9, flux=1, seed=4, start=O.HOT)
+    o.sweep(1, 1)
+    g = P.Lattice(3, (8, 8, 8, 4), 5.9, flux=1, seed=4, start=P.COLD, storage=storage)
+    g.set_links(o.get_links())
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < 1e-6 and maxdiff(lg, lo) < 1e-6
+
+
+def test_su2_fp32_form():
+    g, o = pair(2, (8, 8, 8, 4), 2.3, seed=6, storage=P.F32)
+    assert maxdiff(g.get_links(), o.get_links()) < 1e-7
+    o2 = O.Lattice(2, (8, 8, 8, 4), 2.3, seed=6, start=O.COLD)
+    o2.set_links(g.get_links())
+    g.sweep(0, 1)
+    o2.sweep(0, 1)
+    assert maxdiff(g.get_links(), o2.get_links()) < TOL32
+
+
+def test_full_size_32x8_flux4_one_compound_sweep():
+    """The measured workload's lattice (SU(3) 32^3x8, beta 5.9, n = 4, cold
+    start) in the bench's launch configuration: every link after one
+    (1 HB + 4 OR) sweep against the oracle."""
+    w = su3_32x8(4)
+    g, o = pair(w.group, w.dims, w.beta, flux=w.flux, seed=w.seed, start=O.COLD)
+    O.set_threads(O.get_threads())
+    g.sweep(1, 4)
+    o.sweep(1, 4)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
