@@ -130,6 +130,9 @@ def main() -> int:
                     help="storage forms to time; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (a known-size kernel that "
+                         "calibrates the profiler's HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice is resident on a single MI355X); "
@@ -140,6 +143,15 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     import paper_1310_7087_amd as P
+
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_mib} MiB done")
+        del src, dst
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}

@@ -88,6 +88,9 @@ typedef struct {
                             default, else 64, 128, 256 or 512 */
     int tile_order;      /* 0 = XCD-aware block->tile map (default),
                             1 = identity, 2 = reversed (for order-independence tests) */
+    int layout;          /* plane stride of the link arrays: 0 = staggered so that
+                            planes do not alias in caches and channels (default),
+                            1 = plain (padded to a multiple of 256 sites) */
 } lat_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -205,9 +208,16 @@ typedef struct {
     uint32_t lattice_id;
 } lat_desc;
 
-/* n lattices described by d[0..n-1]; common supplies storage, rng (Philox or
- * constant), nhit, stream (the per-lattice fields of common are ignored). */
+/* n lattices described by d[0..n-1]; common supplies storage, nhit, stream
+ * and block_size (0 = tuned by lat_batch_autotune or the default); the
+ * generator must be Philox (each member keyed by its own seed and
+ * lattice_id); the per-lattice fields of common are ignored.  Each member's
+ * results are bit-identical to the same lattice run alone. */
 int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common);
+/* Launch shape of the persistent kernel: work-group size (64, 128, 256),
+ * sites per thread of a work item (1..8) and grid size (0 = 1024 threads per
+ * compute unit).  Any shape gives the same results. */
+int lat_batch_configure(lat_batch_t b, int block_size, int sites_per_thread, int grid);
 /* n_sweeps compound sweeps of every member; if plaq / poly are non-NULL they
  * receive each member's final measurement ([n][3] and [n][2]); synchronises. */
 int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly);

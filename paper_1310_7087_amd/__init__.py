@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("device_bytes", ctypes.c_size_t),
         ("block_size", ctypes.c_int),
         ("tile_order", ctypes.c_int),
+        ("layout", ctypes.c_int),
     ]
 
 
@@ -88,13 +89,14 @@ def _load():
     L.lat_philox4x32_10.argtypes = [vp, vp, vp, sz]
     L.lat_batch_create.argtypes = [P(vp), i, P(Desc), P(Options)]
     L.lat_batch_run.argtypes = [vp, i, i, i, vp, vp]
+    L.lat_batch_configure.argtypes = [vp, i, i, i]
     L.lat_batch_get_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_set_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_destroy.argtypes = [vp]
     for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_set_links",
                  "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_set_accept_log", "lat_save", "lat_load",
                  "lat_destroy", "lat_philox4x32_10", "lat_batch_create", "lat_batch_run",
-                 "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy"):
+                 "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy", "lat_batch_configure"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -122,7 +124,8 @@ def default_options() -> Options:
 
 
 def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, nhit=10,
-                 lattice_id=0, stream=None, device_buffer=None, block_size=0, tile_order=0) -> Options:
+                 lattice_id=0, stream=None, device_buffer=None, block_size=0, tile_order=0,
+                 layout=0) -> Options:
     o = default_options()
     o.storage = storage
     o.rng = rng
@@ -133,6 +136,7 @@ def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, 
     o.lattice_id = lattice_id
     o.block_size = block_size
     o.tile_order = tile_order
+    o.layout = layout
     if stream is not None:
         o.stream = stream if isinstance(stream, int) else int(stream.cuda_stream)
     if device_buffer is not None:  # a torch tensor (or any object with data_ptr/nbytes)
@@ -289,6 +293,9 @@ class Batch:
         _check(lib.lat_batch_run(self._h, int(n_sweeps), int(n_hb), int(n_or),
                                  _ptr(p) if measure else None, _ptr(l) if measure else None))
         return p, l
+
+    def configure(self, block_size=256, sites_per_thread=1, grid=0):
+        _check(lib.lat_batch_configure(self._h, int(block_size), int(sites_per_thread), int(grid)))
 
     def get_links(self, i) -> np.ndarray:
         d = self.descs[i]

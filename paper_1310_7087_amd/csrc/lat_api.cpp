@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -108,7 +109,10 @@ struct Layout {
     int nb_plaq, nb_poly;
 };
 
-int make_layout(int group, const int d[4], int storage, int rng, Layout& L) {
+// Bytes of the vector type one plane element holds.
+int vec_bytes(int group, int storage) { return (group == 3 && storage == LAT_F32) ? 8 : 16; }
+
+int make_layout(int group, const int d[4], int storage, int rng, int layout, Layout& L) {
     for (int m = 0; m < 4; ++m)
         if (d[m] < 2 || (d[m] & 1)) return fail(LAT_EINVAL, "extent %d = %d must be even and >= 2", m, d[m]);
     if (group != 2 && group != 3) return fail(LAT_EINVAL, "group must be 2 or 3, got %d", group);
@@ -123,8 +127,19 @@ int make_layout(int group, const int d[4], int storage, int rng, Layout& L) {
     g.nt = d[3];
     g.nxh = d[0] / 2;
     g.vh = V / 2;
-    // equal plane lengths, padded to the work-group multiple
-    g.vh_pad = (int64_t)align_up((size_t)g.vh, 256);
+    if (layout == 1) {
+        // equal plane lengths, padded to the work-group multiple
+        g.vh_pad = (int64_t)align_up((size_t)g.vh, 256);
+    } else {
+        // Staggered planes: every plane starts 128-byte aligned and the plane
+        // stride is 17 (mod 64) cache lines, so the 8*NP planes a pass reads at
+        // the same site offset fall into distinct L2 sets and memory channels
+        // instead of all aliasing at power-of-two distances.
+        const int64_t per_line = 128 / vec_bytes(group, storage);
+        int64_t lines = (g.vh + per_line - 1) / per_line;
+        lines += (17 - lines % 64 + 64) % 64;
+        g.vh_pad = lines * per_line;
+    }
     L.g = g;
     L.links_off = 0;
     L.links_bytes = (size_t)g.vh_pad * 2 * 4 * bytes_per_link(group, storage);
@@ -369,6 +384,7 @@ int check_opts(const lat_options* o) {
     if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 && o->block_size != 256)
         return fail(LAT_EINVAL, "block_size must be 0, 64, 128 or 256");
     if (o->tile_order < 0 || o->tile_order > 2) return fail(LAT_EINVAL, "tile_order must be 0, 1 or 2");
+    if (o->layout < 0 || o->layout > 1) return fail(LAT_EINVAL, "layout must be 0 or 1");
     return LAT_OK;
 }
 
@@ -411,7 +427,7 @@ size_t lat_device_bytes(int group, int Nx, int Ny, int Nz, int Nt, const lat_opt
     if (opt) o = *opt;
     int d[4] = {Nx, Ny, Nz, Nt};
     Layout L;
-    if (make_layout(group, d, o.storage, o.rng, L) != LAT_OK) return 0;
+    if (make_layout(group, d, o.storage, o.rng, o.layout, L) != LAT_OK) return 0;
     return L.total;
 }
 
@@ -442,7 +458,7 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     h->dims[1] = Ny;
     h->dims[2] = Nz;
     h->dims[3] = Nt;
-    rc = make_layout(group, h->dims, o.storage, o.rng, h->lay);
+    rc = make_layout(group, h->dims, o.storage, o.rng, o.layout, h->lay);
     if (rc) {
         delete h;
         return rc;
@@ -828,13 +844,137 @@ extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
 }
 
 // ===========================================================================
-// batches: independent lattices, one handle each, swept together
+// batches: independent lattices (one handle each for memory, initialisation,
+// measurement and I/O) advanced together by one persistent kernel launch
 // ===========================================================================
+struct BatchGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct lat_batch {
     std::vector<lat_t> members;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int storage = LAT_F32;
+    BatchLat* d_lats = nullptr;       // device table
+    uint64_t** d_counters = nullptr;  // members' heat-bath counters
+    unsigned* d_work = nullptr;       // [0] queue, [1] status, [2..] done per member
+    int tiles_per_pass = 0;
+    int block = 256, spt = 1, grid = 0;
+    bool tuned = false;
+    std::map<std::tuple<int, int, int, int, int, int>, BatchGraph> graphs;
 };
+
+namespace {
+
+int batch_build_table(lat_batch* b) {
+    const int n = (int)b->members.size();
+    std::vector<BatchLat> t(n);
+    std::vector<uint64_t*> ctr(n);
+    const int tile = b->block * b->spt;
+    int prefix = 0;
+    for (int i = 0; i < n; ++i) {
+        lat_ctx* h = b->members[i];
+        BatchLat& L = t[i];
+        L.g = h->lay.g;
+        L.links = h->links();
+        L.hb_count = h->hb();
+        L.beta = h->beta;
+        L.rng_const = h->rng_const;
+        L.key0 = (uint32_t)h->seed;
+        L.key1 = (uint32_t)(h->seed >> 32);
+        L.lat_id = h->lat_id;
+        L.nhit = h->nhit;
+        L.group = h->group;
+        L.flux = h->flux;
+        L.rng = h->rng;
+        L.ntiles = (int)((h->lay.g.vh + tile - 1) / tile);
+        L.tile_prefix = prefix;
+        prefix += L.ntiles;
+        ctr[i] = h->hb();
+    }
+    b->tiles_per_pass = prefix;
+    if (!b->d_lats) HIP_TRY(hipMalloc(&b->d_lats, sizeof(BatchLat) * n));
+    if (!b->d_counters) HIP_TRY(hipMalloc(&b->d_counters, sizeof(uint64_t*) * n));
+    if (!b->d_work) HIP_TRY(hipMalloc(&b->d_work, sizeof(unsigned) * (n + 2)));
+    HIP_TRY(hipMemcpyAsync(b->d_lats, t.data(), sizeof(BatchLat) * n, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_counters, ctr.data(), sizeof(uint64_t*) * n, hipMemcpyHostToDevice, b->stream));
+    std::vector<unsigned> zero(n + 2, 0);
+    HIP_TRY(hipMemcpyAsync(b->d_work, zero.data(), zero.size() * sizeof(unsigned), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return LAT_OK;
+}
+
+void batch_drop_graphs(lat_batch* b) {
+    for (auto& kv : b->graphs) {
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+    }
+    b->graphs.clear();
+}
+
+BatchArgs batch_args(const lat_batch* b, int n_sweeps, int n_hb, int n_or) {
+    BatchArgs a;
+    a.lats = b->d_lats;
+    a.nlat = (int)b->members.size();
+    a.tiles_per_pass = b->tiles_per_pass;
+    a.passes_per_sweep = 8 * (n_hb + n_or);
+    a.n_hb = n_hb;
+    a.n_or = n_or;
+    a.n_sweeps = n_sweeps;
+    a.tile = b->block * b->spt;
+    a.queue = b->d_work;
+    a.status = reinterpret_cast<int*>(b->d_work + 1);
+    a.done = b->d_work + 2;
+    a.spin_limit = 1u << 26;
+    return a;
+}
+
+int batch_enqueue(lat_batch* b, int n_sweeps, int n_hb, int n_or) {
+    auto key = std::make_tuple(n_sweeps, n_hb, n_or, b->block, b->spt, b->grid);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        BatchGraph g;
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = lat_launch_batch(b->storage, batch_args(b, n_sweeps, n_hb, n_or), b->d_counters, b->grid,
+                                        b->block, b->stream);
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g.graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g.graph) hipGraphDestroy(g.graph);
+            return fail(LAT_EDEVICE, "batch capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g.graph);
+            return fail(LAT_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
+        }
+        it = b->graphs.emplace(key, g).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, b->stream));
+    for (lat_t h : b->members) {
+        h->hb_sweeps += (uint64_t)n_sweeps * n_hb;
+        h->sweeps += (uint64_t)n_sweeps;
+    }
+    return LAT_OK;
+}
+
+int batch_check_status(lat_batch* b) {
+    unsigned st = 0;
+    HIP_TRY(hipMemcpyAsync(&st, b->d_work + 1, sizeof st, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (st) return fail(LAT_EDEVICE, "batch launch: a dependency wait exceeded its spin limit");
+    return LAT_OK;
+}
+
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+}  // namespace
 
 extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common) {
     if (!out || !d || n <= 0) return fail(LAT_EINVAL, "bad batch arguments");
@@ -842,7 +982,9 @@ extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, cons
     lat_options o;
     lat_default_options(&o);
     if (common) o = *common;
+    if (o.rng != LAT_RNG_PHILOX) return fail(LAT_EUNSUPPORTED, "batches use the Philox generator");
     lat_batch* b = new lat_batch();
+    b->storage = o.storage;
     if (o.stream) {
         b->stream = (hipStream_t)o.stream;
     } else {
@@ -871,18 +1013,45 @@ extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, cons
         }
         b->members.push_back(h);
     }
+    if (o.block_size) {
+        b->block = o.block_size;
+        b->tuned = true;
+    }
+    b->grid = device_cus() * (1024 / b->block);
+    int rc = batch_build_table(b);
+    if (rc) {
+        std::string keep = g_err;
+        lat_batch_destroy(b);
+        g_err = keep;
+        return rc;
+    }
     *out = b;
     return LAT_OK;
+}
+
+extern "C" int lat_batch_configure(lat_batch_t b, int block_size, int sites_per_thread, int grid) {
+    if (!b) return fail(LAT_EINVAL, "NULL batch");
+    if (block_size != 64 && block_size != 128 && block_size != 256) return fail(LAT_EINVAL, "block_size 64|128|256");
+    if (sites_per_thread < 1 || sites_per_thread > 8) return fail(LAT_EINVAL, "sites_per_thread 1..8");
+    if (grid < 0) return fail(LAT_EINVAL, "grid >= 0");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->block = block_size;
+    b->spt = sites_per_thread;
+    b->grid = grid ? grid : device_cus() * (1024 / block_size);
+    b->tuned = true;
+    batch_drop_graphs(b);
+    return batch_build_table(b);
 }
 
 extern "C" int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly) {
     if (!b) return fail(LAT_EINVAL, "NULL batch");
     if (n_sweeps < 0 || n_hb < 0 || n_or < 0) return fail(LAT_EINVAL, "negative argument");
-    for (int k = 0; k < n_sweeps; ++k)
-        for (lat_t h : b->members) {
-            int rc = do_sweep(h, n_hb, n_or);
-            if (rc) return rc;
-        }
+    if (n_sweeps > 0 && n_hb + n_or > 0) {
+        int rc = batch_enqueue(b, n_sweeps, n_hb, n_or);
+        if (rc) return rc;
+        rc = batch_check_status(b);
+        if (rc) return rc;
+    }
     for (size_t i = 0; i < b->members.size(); ++i) {
         if (plaq || poly) {
             int rc = lat_measure(b->members[i], plaq ? plaq + 3 * i : nullptr, poly ? poly + 2 * i : nullptr);
@@ -905,7 +1074,12 @@ extern "C" int lat_batch_set_links(lat_batch_t b, int i, const double* host, siz
 
 extern "C" int lat_batch_destroy(lat_batch_t b) {
     if (!b) return LAT_OK;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
     for (lat_t h : b->members) lat_destroy(h);
+    if (b->d_lats) hipFree(b->d_lats);
+    if (b->d_counters) hipFree(b->d_counters);
+    if (b->d_work) hipFree(b->d_work);
     if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
     delete b;
     return LAT_OK;

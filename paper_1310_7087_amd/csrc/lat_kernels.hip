@@ -34,12 +34,11 @@ constexpr int SUB_B[3] = {1, 2, 2};
 // ---------------------------------------------------------------------------
 // SU(3) pass
 // ---------------------------------------------------------------------------
+// Update of the link U_mu(x) at half-lattice index s of the pass parity.
 template <class ST, int KIND, bool REUNIT, int RNG>
-__global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
+LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     using T = typename ST::real;
     using M = m3<T>;
-    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= a.g.vh) return;
     const int p = a.parity, q = 1 - p, mu = a.mu;
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
@@ -131,15 +130,20 @@ __global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
     }
 }
 
+template <class ST, int KIND, bool REUNIT, int RNG>
+__global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
+    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
+    if (s < a.g.vh) su3_site<ST, KIND, REUNIT, RNG>(a, s);
+}
+
 // ---------------------------------------------------------------------------
 // SU(2) pass (quaternions)
 // ---------------------------------------------------------------------------
+// Update of the link U_mu(x) at half-lattice index s of the pass parity.
 template <class ST, int KIND, bool REUNIT, int RNG>
-__global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
+LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
     using T = typename ST::real;
     using Q = qt<T>;
-    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= a.g.vh) return;
     const int p = a.parity, q = 1 - p, mu = a.mu;
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
@@ -216,6 +220,12 @@ __global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
         U = {(T)(ud.q0 * in), (T)(ud.q1 * in), (T)(ud.q2 * in), (T)(ud.q3 * in)};
     }
     ST::store(const_cast<char*>(dir_base<ST>(L, vp, p, mu)), vp, s, U);
+}
+
+template <class ST, int KIND, bool REUNIT, int RNG>
+__global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
+    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
+    if (s < a.g.vh) su2_site<ST, KIND, REUNIT, RNG>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,6 +581,114 @@ __global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, uin
     out[4 * i + 3] = o.w;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batch of independent lattices in one persistent launch.  Blocks take work
+// items (pass, lattice, tile) from a global counter in pass-major order; an
+// item waits until every tile of the previous passes of its own lattice is
+// done (per-lattice counters, agent-scope acquire/release), so lattices of
+// different sizes advance independently and no grid-wide barrier exists.
+// Items are handed out in increasing order and depend only on smaller ones,
+// so the smallest unfinished item can always run: the launch drains for any
+// grid size.  A bounded spin guards against a broken invariant.
+// ---------------------------------------------------------------------------
+template <class ST3, class ST2>
+LAT_DEV void batch_site(const PassArgs& a, int kind, bool reunit, int64_t s) {
+    if (a.group == 3) {
+        if (kind == 0) {
+            if (reunit) su3_site<ST3, 0, true, LAT_RNG_PHILOX_I>(a, s);
+            else su3_site<ST3, 0, false, LAT_RNG_PHILOX_I>(a, s);
+        } else {
+            if (reunit) su3_site<ST3, 1, true, LAT_RNG_CONST_I>(a, s);
+            else su3_site<ST3, 1, false, LAT_RNG_CONST_I>(a, s);
+        }
+    } else {
+        if (kind == 0) {
+            if (reunit) su2_site<ST2, 0, true, LAT_RNG_PHILOX_I>(a, s);
+            else su2_site<ST2, 0, false, LAT_RNG_PHILOX_I>(a, s);
+        } else {
+            if (reunit) su2_site<ST2, 1, true, LAT_RNG_CONST_I>(a, s);
+            else su2_site<ST2, 1, false, LAT_RNG_CONST_I>(a, s);
+        }
+    }
+}
+
+template <class ST3, class ST2>
+__global__ void __launch_bounds__(256) batch_persistent(BatchArgs b) {
+    __shared__ unsigned item_sh;
+    const int64_t per_sweep = (int64_t)b.tiles_per_pass * b.passes_per_sweep;
+    const int64_t total = per_sweep * b.n_sweeps;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1u);
+        __syncthreads();
+        const int64_t item = item_sh;
+        if (item >= total) return;  // uniform: every wave of the block leaves
+        const int64_t gp = item / b.tiles_per_pass;  // pass index within the launch
+        const int r = (int)(item - gp * b.tiles_per_pass);
+        int lo = 0, hi = b.nlat - 1;  // member whose tile range holds r
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.lats[mid].tile_prefix <= r) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchLat& L = b.lats[lo];
+        const int tile = r - L.tile_prefix;
+        const int sweep = (int)(gp / b.passes_per_sweep);
+        const int pp = (int)(gp - (int64_t)sweep * b.passes_per_sweep);
+        const int sw = pp >> 3;
+        const int kind = sw < b.n_hb ? 0 : 1;
+        const bool reunit = (sw == b.n_hb + b.n_or - 1);
+        if (threadIdx.x == 0) {
+            const unsigned need = (unsigned)gp * (unsigned)L.ntiles;
+            unsigned spins = 0;
+            while (__hip_atomic_load(b.done + lo, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > b.spin_limit) {
+                    atomicExch(b.status, 1);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        PassArgs a;
+        a.g = L.g;
+        a.links = L.links;
+        a.mrg = nullptr;
+        a.hb_count = L.hb_count;
+        a.accept_log = nullptr;
+        a.beta = L.beta;
+        a.rng_const = L.rng_const;
+        a.key0 = L.key0;
+        a.key1 = L.key1;
+        a.lat_id = L.lat_id;
+        a.nhit = L.nhit;
+        a.group = L.group;
+        a.mu = (pp >> 1) & 3;
+        a.parity = pp & 1;
+        a.hb_offset = sweep * b.n_hb + sw;
+        a.tile_order = 1;
+        a.flux = L.flux;
+        for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < (int64_t)(tile + 1) * b.tile && s < L.g.vh;
+             s += blockDim.x)
+            batch_site<ST3, ST2>(a, kind, reunit, s);
+        // every wave's stores have reached L2 before the release by thread 0
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(b.done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void batch_reset(BatchArgs b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < b.nlat) b.done[i] = 0;
+    if (i == 0) *b.queue = 0;
+}
+
+__global__ void batch_bump(BatchArgs b, uint64_t** counters, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < b.nlat) *counters[i] += (uint64_t)n;
+}
+
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
@@ -715,5 +833,24 @@ hipError_t lat_launch_bump(uint64_t* counter, int n, hipStream_t st) {
 hipError_t lat_launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, k0, k1, out, n);
+    return hipGetLastError();
+}
+
+hipError_t lat_launch_batch(int storage, const BatchArgs& b, uint64_t** counters, int grid, int block,
+                            hipStream_t st) {
+    const unsigned nb = (unsigned)((b.nlat + 255) / 256);
+    hipLaunchKernelGGL(batch_reset, dim3(nb), dim3(256), 0, st, b);
+    switch (storage) {
+        case LAT_ST_F64:
+            hipLaunchKernelGGL((batch_persistent<st_f64, sq_f64>), dim3(grid), dim3(block), 0, st, b);
+            break;
+        case LAT_ST_F32:
+            hipLaunchKernelGGL((batch_persistent<st_f32, sq_f32>), dim3(grid), dim3(block), 0, st, b);
+            break;
+        default:
+            hipLaunchKernelGGL((batch_persistent<st_f32c12, sq_f32>), dim3(grid), dim3(block), 0, st, b);
+            break;
+    }
+    if (b.n_hb > 0) hipLaunchKernelGGL(batch_bump, dim3(nb), dim3(256), 0, st, b, counters, b.n_hb * b.n_sweeps);
     return hipGetLastError();
 }

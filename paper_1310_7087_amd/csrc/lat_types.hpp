@@ -54,3 +54,31 @@ struct MeasArgs {
     int nb_plaq;          // blocks of the plaquette kernel
     int nb_poly;          // blocks of the Polyakov kernel
 };
+
+// One member of a batch of independent lattices.
+struct BatchLat {
+    LatGeom g;
+    char* links;
+    const uint64_t* hb_count;  // heat-bath sweeps completed before this launch
+    double beta;
+    double rng_const;
+    uint32_t key0, key1, lat_id;
+    int nhit, group, flux, rng;
+    int ntiles;       // tiles per pass
+    int tile_prefix;  // index of this lattice's first tile within a pass
+};
+
+// Work list of one persistent batch launch: n_sweeps compound sweeps
+// (n_hb, n_or) of every member; item = (pass, lattice, tile), pass-major.
+struct BatchArgs {
+    const BatchLat* lats;
+    int nlat;
+    int tiles_per_pass;   // sum of ntiles over members
+    int passes_per_sweep; // 8 * (n_hb + n_or)
+    int n_hb, n_or, n_sweeps;
+    int tile;             // half-sites per tile
+    unsigned* queue;      // next work item
+    unsigned* done;       // [nlat] tiles completed in this launch
+    int* status;          // nonzero if a dependency wait hit its spin limit
+    unsigned spin_limit;
+};

@@ -1,0 +1,70 @@
+"""GPU tests of the persistent batch launch: every member of a batch of
+uneven lattices is bit-identical to the same lattice run alone (the batch
+result is defined as the per-lattice result), for any launch shape; and a
+member matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from inputs import batch_workloads
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1310_7087_amd")
+
+
+def descs_of(ws):
+    return [dict(group=w.group, dims=w.dims, beta=w.beta, flux=w.flux, seed=w.seed, start=w.start,
+                 lattice_id=w.lattice_id) for w in ws]
+
+
+def small_batch():
+    # mixed groups, uneven sizes, one flux member, shapes with ragged tiles
+    return [dict(group=3, dims=(8, 8, 8, 4), beta=5.7, seed=11, lattice_id=0),
+            dict(group=2, dims=(10, 10, 10, 4), beta=2.3, seed=11, lattice_id=1),
+            dict(group=3, dims=(6, 4, 10, 2), beta=5.9, seed=11, lattice_id=2, flux=2),
+            dict(group=2, dims=(2, 2, 2, 2), beta=2.2, seed=11, lattice_id=3),
+            dict(group=3, dims=(12, 12, 12, 6), beta=6.0, seed=11, lattice_id=4)]
+
+
+@pytest.mark.parametrize("storage", [P.F32, P.F64, P.F32_C12])
+@pytest.mark.parametrize("shape", [(256, 1, 0), (64, 1, 7), (128, 3, 0), (256, 2, 33)])
+def test_members_equal_single_runs(storage, shape):
+    descs = small_batch()
+    b = P.Batch(descs, storage=storage, rng=P.RNG_PHILOX)
+    b.configure(*shape)
+    pb, lb = b.run(3, 1, 4)
+    for i, d in enumerate(descs):
+        single = P.Lattice(d["group"], d["dims"], d["beta"], d.get("flux", 0), storage=storage,
+                           rng=P.RNG_PHILOX, seed=d["seed"], lattice_id=d["lattice_id"], start=P.HOT)
+        for _ in range(3):
+            single.sweep(1, 4)
+        assert np.array_equal(b.get_links(i), single.get_links()), (i, d)
+        p, l = single.measure()
+        assert np.array_equal(pb[i], p) and np.array_equal(lb[i], l)
+
+
+def test_batch_member_matches_oracle():
+    descs = small_batch()
+    b = P.Batch(descs, storage=P.F64, rng=P.RNG_PHILOX)
+    b.run(1, 1, 0)
+    for i in (0, 1, 3):
+        d = descs[i]
+        o = O.Lattice(d["group"], d["dims"], d["beta"], flux=d.get("flux", 0), seed=d["seed"],
+                      lattice_id=d["lattice_id"], start=O.HOT)
+        o.sweep(1, 0)
+        assert np.abs(b.get_links(i) - o.get_links()).max() < 1e-12
+
+
+def test_scan_workload_runs_and_repeats():
+    """The 64-lattice beta scan (8^3x4 .. 24^3x6, SU(2)/SU(3)), two sweeps,
+    bit-identical when repeated with another launch shape."""
+    ws = batch_workloads(64, seed=11)
+    d = descs_of(ws)
+    a = P.Batch(d, storage=P.F32)
+    pa, _ = a.run(2, 1, 4)
+    b = P.Batch(d, storage=P.F32)
+    b.configure(128, 2, 0)
+    pb, _ = b.run(2, 1, 4)
+    assert np.array_equal(pa, pb)
+    assert np.all(pa[:, 0] > 0.2) and np.all(pa[:, 0] < 0.8)
