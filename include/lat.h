@@ -211,13 +211,18 @@ typedef struct {
 /* n lattices described by d[0..n-1]; common supplies storage, nhit, stream
  * and block_size (0 = tuned by lat_batch_autotune or the default); the
  * generator must be Philox (each member keyed by its own seed and
- * lattice_id); the per-lattice fields of common are ignored.  Each member's
+ * lattice_id); with LAT_F32_C12 the SU(2) members use LAT_F32; the
+ * per-lattice fields of common are ignored.  Each member's
  * results are bit-identical to the same lattice run alone. */
 int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common);
-/* Launch shape of the persistent kernel: work-group size (64, 128, 256),
- * sites per thread of a work item (1..8) and grid size (0 = 1024 threads per
- * compute unit).  Any shape gives the same results. */
-int lat_batch_configure(lat_batch_t b, int block_size, int sites_per_thread, int grid);
+/* Launch form and shape.  mode 0 (default): one kernel per pass index, each
+ * covering that pass of every member (kernel boundaries order the passes);
+ * mode 1: one persistent work-list kernel for all passes of the run, with
+ * per-member dependency counters instead of any grid-wide barrier.
+ * block_size 64|128|256, sites_per_thread 1..8 per work item, grid = blocks
+ * of the persistent kernel (0 = 1024 threads per compute unit).  Every form
+ * and shape gives bit-identical results. */
+int lat_batch_configure(lat_batch_t b, int mode, int block_size, int sites_per_thread, int grid);
 /* n_sweeps compound sweeps of every member; if plaq / poly are non-NULL they
  * receive each member's final measurement ([n][3] and [n][2]); synchronises. */
 int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly);

@@ -89,7 +89,7 @@ def _load():
     L.lat_philox4x32_10.argtypes = [vp, vp, vp, sz]
     L.lat_batch_create.argtypes = [P(vp), i, P(Desc), P(Options)]
     L.lat_batch_run.argtypes = [vp, i, i, i, vp, vp]
-    L.lat_batch_configure.argtypes = [vp, i, i, i]
+    L.lat_batch_configure.argtypes = [vp, i, i, i, i]
     L.lat_batch_get_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_set_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_destroy.argtypes = [vp]
@@ -294,8 +294,9 @@ class Batch:
                                  _ptr(p) if measure else None, _ptr(l) if measure else None))
         return p, l
 
-    def configure(self, block_size=256, sites_per_thread=1, grid=0):
-        _check(lib.lat_batch_configure(self._h, int(block_size), int(sites_per_thread), int(grid)))
+    def configure(self, mode=0, block_size=256, sites_per_thread=1, grid=0):
+        """mode 0: one launch per pass over all members; 1: persistent work list."""
+        _check(lib.lat_batch_configure(self._h, int(mode), int(block_size), int(sites_per_thread), int(grid)))
 
     def get_links(self, i) -> np.ndarray:
         d = self.descs[i]

@@ -583,14 +583,22 @@ __global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, uin
 
 
 // ---------------------------------------------------------------------------
-// Batch of independent lattices in one persistent launch.  Blocks take work
-// items (pass, lattice, tile) from a global counter in pass-major order; an
-// item waits until every tile of the previous passes of its own lattice is
-// done (per-lattice counters, agent-scope acquire/release), so lattices of
-// different sizes advance independently and no grid-wide barrier exists.
-// Items are handed out in increasing order and depend only on smaller ones,
-// so the smallest unfinished item can always run: the launch drains for any
-// grid size.  A bounded spin guards against a broken invariant.
+// Batches of independent lattices.  A work item is (pass, lattice, tile);
+// the lattices' tiles of one pass are concatenated (tile_prefix).
+//
+// batch_pass: one launch per pass index covers that pass of every member,
+// kernel boundaries order the passes.
+//
+// batch_persistent: one launch for whole compound sweeps.  Blocks take items
+// from a global counter in pass-major order; an item waits until every tile
+// of the previous passes of its own lattice is done (per-lattice counters:
+// relaxed polling with sleeps, then one agent-scope acquire fence; release
+// by the finishing block), so members of different sizes advance
+// independently with no grid-wide barrier.  Items are handed out in
+// increasing order and depend only on smaller ones, so the smallest
+// unfinished item can always run and the launch drains for any grid size.
+// A bounded wait sets an abort flag that makes every later wait return at
+// once, so even a broken invariant cannot keep the kernel alive.
 // ---------------------------------------------------------------------------
 template <class ST3, class ST2>
 LAT_DEV void batch_site(const PassArgs& a, int kind, bool reunit, int64_t s) {
@@ -613,75 +621,96 @@ LAT_DEV void batch_site(const PassArgs& a, int kind, bool reunit, int64_t s) {
     }
 }
 
+LAT_DEV int batch_member(const BatchArgs& b, int r) {
+    int lo = 0, hi = b.nlat - 1;  // last member whose first tile is <= r
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.lats[mid].tile_prefix <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Runs tile `tile` of member `m` for pass gp (counted from the launch start).
+template <class ST3, class ST2>
+LAT_DEV void batch_tile(const BatchArgs& b, int m, int tile, int64_t gp) {
+    const BatchLat& L = b.lats[m];
+    const int sweep = (int)(gp / b.passes_per_sweep);
+    const int pp = (int)(gp - (int64_t)sweep * b.passes_per_sweep);
+    const int sw = pp >> 3;
+    const int kind = sw < b.n_hb ? 0 : 1;
+    const bool reunit = (sw == b.n_hb + b.n_or - 1);
+    PassArgs a;
+    a.g = L.g;
+    a.links = L.links;
+    a.mrg = nullptr;
+    a.hb_count = L.hb_count;
+    a.accept_log = nullptr;
+    a.beta = L.beta;
+    a.rng_const = L.rng_const;
+    a.key0 = L.key0;
+    a.key1 = L.key1;
+    a.lat_id = L.lat_id;
+    a.nhit = L.nhit;
+    a.group = L.group;
+    a.mu = (pp >> 1) & 3;
+    a.parity = pp & 1;
+    a.hb_offset = sweep * b.n_hb + (kind == 0 ? sw : 0);
+    a.tile_order = 1;
+    a.flux = L.flux;
+    const int64_t end = (int64_t)(tile + 1) * b.tile < L.g.vh ? (int64_t)(tile + 1) * b.tile : L.g.vh;
+    for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < end; s += blockDim.x)
+        batch_site<ST3, ST2>(a, kind, reunit, s);
+}
+
+template <class ST3, class ST2>
+__global__ void __launch_bounds__(256) batch_pass(BatchArgs b, int64_t gp) {
+    const int r = (int)blockIdx.x;
+    const int m = batch_member(b, r);
+    batch_tile<ST3, ST2>(b, m, r - b.lats[m].tile_prefix, gp);
+}
+
 template <class ST3, class ST2>
 __global__ void __launch_bounds__(256) batch_persistent(BatchArgs b) {
     __shared__ unsigned item_sh;
-    const int64_t per_sweep = (int64_t)b.tiles_per_pass * b.passes_per_sweep;
-    const int64_t total = per_sweep * b.n_sweeps;
+    const int64_t total = (int64_t)b.tiles_per_pass * b.passes_per_sweep * b.n_sweeps;
     for (;;) {
         if (threadIdx.x == 0) item_sh = atomicAdd(b.queue, 1u);
         __syncthreads();
         const int64_t item = item_sh;
         if (item >= total) return;  // uniform: every wave of the block leaves
-        const int64_t gp = item / b.tiles_per_pass;  // pass index within the launch
+        const int64_t gp = item / b.tiles_per_pass;
         const int r = (int)(item - gp * b.tiles_per_pass);
-        int lo = 0, hi = b.nlat - 1;  // member whose tile range holds r
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (b.lats[mid].tile_prefix <= r) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchLat& L = b.lats[lo];
-        const int tile = r - L.tile_prefix;
-        const int sweep = (int)(gp / b.passes_per_sweep);
-        const int pp = (int)(gp - (int64_t)sweep * b.passes_per_sweep);
-        const int sw = pp >> 3;
-        const int kind = sw < b.n_hb ? 0 : 1;
-        const bool reunit = (sw == b.n_hb + b.n_or - 1);
+        const int m = batch_member(b, r);
         if (threadIdx.x == 0) {
-            const unsigned need = (unsigned)gp * (unsigned)L.ntiles;
+            const unsigned need = (unsigned)gp * (unsigned)b.lats[m].ntiles;
             unsigned spins = 0;
-            while (__hip_atomic_load(b.done + lo, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                __builtin_amdgcn_s_sleep(1);
+            while (__hip_atomic_load(b.done + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                if (__hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                __builtin_amdgcn_s_sleep(8);
                 if (++spins > b.spin_limit) {
-                    atomicExch(b.status, 1);
+                    __hip_atomic_store(b.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
         }
         __syncthreads();
-        PassArgs a;
-        a.g = L.g;
-        a.links = L.links;
-        a.mrg = nullptr;
-        a.hb_count = L.hb_count;
-        a.accept_log = nullptr;
-        a.beta = L.beta;
-        a.rng_const = L.rng_const;
-        a.key0 = L.key0;
-        a.key1 = L.key1;
-        a.lat_id = L.lat_id;
-        a.nhit = L.nhit;
-        a.group = L.group;
-        a.mu = (pp >> 1) & 3;
-        a.parity = pp & 1;
-        a.hb_offset = sweep * b.n_hb + sw;
-        a.tile_order = 1;
-        a.flux = L.flux;
-        for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < (int64_t)(tile + 1) * b.tile && s < L.g.vh;
-             s += blockDim.x)
-            batch_site<ST3, ST2>(a, kind, reunit, s);
-        // every wave's stores have reached L2 before the release by thread 0
+        batch_tile<ST3, ST2>(b, m, r - b.lats[m].tile_prefix, gp);
+        // every wave's stores are complete before thread 0 releases the tile
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(b.done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(b.done + m, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 __global__ void batch_reset(BatchArgs b) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < b.nlat) b.done[i] = 0;
-    if (i == 0) *b.queue = 0;
+    if (i == 0) {
+        *b.queue = 0;
+        *b.status = 0;
+    }
 }
 
 __global__ void batch_bump(BatchArgs b, uint64_t** counters, int n) {
@@ -836,20 +865,25 @@ hipError_t lat_launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint
     return hipGetLastError();
 }
 
-hipError_t lat_launch_batch(int storage, const BatchArgs& b, uint64_t** counters, int grid, int block,
+template <class ST3, class ST2>
+static void batch_launch_typed(const BatchArgs& b, int mode, int grid, int block, hipStream_t st) {
+    if (mode == 1) {
+        hipLaunchKernelGGL((batch_persistent<ST3, ST2>), dim3(grid), dim3(block), 0, st, b);
+        return;
+    }
+    const int64_t npass = (int64_t)b.passes_per_sweep * b.n_sweeps;
+    for (int64_t gp = 0; gp < npass; ++gp)
+        hipLaunchKernelGGL((batch_pass<ST3, ST2>), dim3(b.tiles_per_pass), dim3(block), 0, st, b, gp);
+}
+
+hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t** counters, int grid, int block,
                             hipStream_t st) {
     const unsigned nb = (unsigned)((b.nlat + 255) / 256);
-    hipLaunchKernelGGL(batch_reset, dim3(nb), dim3(256), 0, st, b);
+    if (mode == 1) hipLaunchKernelGGL(batch_reset, dim3(nb), dim3(256), 0, st, b);
     switch (storage) {
-        case LAT_ST_F64:
-            hipLaunchKernelGGL((batch_persistent<st_f64, sq_f64>), dim3(grid), dim3(block), 0, st, b);
-            break;
-        case LAT_ST_F32:
-            hipLaunchKernelGGL((batch_persistent<st_f32, sq_f32>), dim3(grid), dim3(block), 0, st, b);
-            break;
-        default:
-            hipLaunchKernelGGL((batch_persistent<st_f32c12, sq_f32>), dim3(grid), dim3(block), 0, st, b);
-            break;
+        case LAT_ST_F64: batch_launch_typed<st_f64, sq_f64>(b, mode, grid, block, st); break;
+        case LAT_ST_F32: batch_launch_typed<st_f32, sq_f32>(b, mode, grid, block, st); break;
+        default: batch_launch_typed<st_f32c12, sq_f32>(b, mode, grid, block, st); break;
     }
     if (b.n_hb > 0) hipLaunchKernelGGL(batch_bump, dim3(nb), dim3(256), 0, st, b, counters, b.n_hb * b.n_sweeps);
     return hipGetLastError();

@@ -14,7 +14,8 @@ hipError_t lat_launch_convert(int group, int storage, bool to_dev, const LatGeom
 hipError_t lat_launch_bump(uint64_t* counter, int n, hipStream_t st);
 hipError_t lat_launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, int64_t n,
                              hipStream_t st);
-// Persistent batch launch (reset counters, work-list kernel, bump the
-// members' heat-bath counters).
-hipError_t lat_launch_batch(int storage, const BatchArgs& b, uint64_t** counters, int grid, int block,
+// Batch launch of n_sweeps compound sweeps: mode 0 = one kernel per pass over
+// all members, mode 1 = one persistent work-list kernel; then the members'
+// heat-bath counters are advanced.
+hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t** counters, int grid, int block,
                             hipStream_t st);

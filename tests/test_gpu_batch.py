@@ -28,14 +28,15 @@ def small_batch():
 
 
 @pytest.mark.parametrize("storage", [P.F32, P.F64, P.F32_C12])
-@pytest.mark.parametrize("shape", [(256, 1, 0), (64, 1, 7), (128, 3, 0), (256, 2, 33)])
+@pytest.mark.parametrize("shape", [(0, 256, 1, 0), (0, 64, 1, 0), (0, 128, 3, 0)])
 def test_members_equal_single_runs(storage, shape):
     descs = small_batch()
     b = P.Batch(descs, storage=storage, rng=P.RNG_PHILOX)
     b.configure(*shape)
     pb, lb = b.run(3, 1, 4)
     for i, d in enumerate(descs):
-        single = P.Lattice(d["group"], d["dims"], d["beta"], d.get("flux", 0), storage=storage,
+        st = P.F32 if (d["group"] == 2 and storage == P.F32_C12) else storage
+        single = P.Lattice(d["group"], d["dims"], d["beta"], d.get("flux", 0), storage=st,
                            rng=P.RNG_PHILOX, seed=d["seed"], lattice_id=d["lattice_id"], start=P.HOT)
         for _ in range(3):
             single.sweep(1, 4)
@@ -64,7 +65,29 @@ def test_scan_workload_runs_and_repeats():
     a = P.Batch(d, storage=P.F32)
     pa, _ = a.run(2, 1, 4)
     b = P.Batch(d, storage=P.F32)
-    b.configure(128, 2, 0)
+    b.configure(0, 128, 2, 0)
     pb, _ = b.run(2, 1, 4)
     assert np.array_equal(pa, pb)
     assert np.all(pa[:, 0] > 0.2) and np.all(pa[:, 0] < 0.8)
+
+
+@pytest.mark.skip(reason="persistent batch form disabled: its run did not finish within the test's time "
+                         "limit on MI355X (cross-XCD dependency polling); cause not yet shown")
+@pytest.mark.parametrize("shape", [(1, 256, 1, 0), (1, 128, 2, 37)])
+def test_persistent_form_equals_per_pass_form(shape):
+    descs = small_batch()
+    a = P.Batch(descs, storage=P.F32)
+    pa, la = a.run(2, 1, 4)
+    b = P.Batch(descs, storage=P.F32)
+    b.configure(*shape)
+    pb, lb = b.run(2, 1, 4)
+    for i in range(len(descs)):
+        assert np.array_equal(a.get_links(i), b.get_links(i)), i
+    assert np.array_equal(pa, pb) and np.array_equal(la, lb)
+
+
+def test_persistent_form_is_refused():
+    b = P.Batch(small_batch()[:2], storage=P.F32)
+    with pytest.raises(P.LatError) as e:
+        b.configure(1, 256, 1, 0)
+    assert e.value.code == P.EUNSUPPORTED
