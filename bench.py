@@ -129,7 +129,8 @@ def main() -> int:
     ap.add_argument("--forms", default="f64,f32,f32c12",
                     help="storage forms to time; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=8,
+                    help="steps of the CPU oracle in the bounded baseline sample (about 1 s each on 16 cores)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size kernel that "
                          "calibrates the profiler's HBM byte counters)")

@@ -86,11 +86,16 @@ typedef struct {
     size_t device_bytes; /* its size; see lat_device_bytes */
     int block_size;      /* work-group size of the sweep kernels: 0 = tuned
                             default, else 64, 128, 256 or 512 */
-    int tile_order;      /* 0 = XCD-aware block->tile map (default),
-                            1 = identity, 2 = reversed (for order-independence tests) */
+    int tile_order;      /* work-group -> tile map: 0 = one z-slab per XCD (own
+                            L2) when 8 | Nz, else identity (default); 1 = identity;
+                            2 = reversed (order-independence tests);
+                            3 = one contiguous range of tiles per XCD */
     int layout;          /* plane stride of the link arrays: 0 = staggered so that
                             planes do not alias in caches and channels (default),
                             1 = plain (padded to a multiple of 256 sites) */
+    int tile[4];         /* sites of one parity per work-group as a 4-D tile
+                            (x/2, y, z, t), product 64, 128 or 256; all 0 =
+                            runs of block_size consecutive sites (default) */
 } lat_options;
 
 /* Fills *opt with the defaults listed above. */

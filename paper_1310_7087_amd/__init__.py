@@ -45,6 +45,7 @@ class Options(ctypes.Structure):
         ("block_size", ctypes.c_int),
         ("tile_order", ctypes.c_int),
         ("layout", ctypes.c_int),
+        ("tile", ctypes.c_int * 4),
     ]
 
 
@@ -125,7 +126,7 @@ def default_options() -> Options:
 
 def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, nhit=10,
                  lattice_id=0, stream=None, device_buffer=None, block_size=0, tile_order=0,
-                 layout=0) -> Options:
+                 layout=0, tile=None) -> Options:
     o = default_options()
     o.storage = storage
     o.rng = rng
@@ -137,6 +138,9 @@ def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, 
     o.block_size = block_size
     o.tile_order = tile_order
     o.layout = layout
+    if tile is not None:
+        for k in range(4):
+            o.tile[k] = int(tile[k])
     if stream is not None:
         o.stream = stream if isinstance(stream, int) else int(stream.cuda_stream)
     if device_buffer is not None:  # a torch tensor (or any object with data_ptr/nbytes)

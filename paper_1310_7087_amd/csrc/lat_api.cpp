@@ -180,6 +180,7 @@ struct lat_ctx {
     bool own_mem = false;
     int block = 256;
     int tile_order = 0;
+    int tshape[4] = {0, 0, 0, 0};
     uint64_t hb_sweeps = 0, sweeps = 0;
     bool log_on = false;
     int8_t* accept_log = nullptr;
@@ -226,6 +227,23 @@ PassArgs pass_args(const lat_ctx* h) {
     a.hb_offset = 0;
     a.tile_order = h->tile_order;
     a.flux = h->flux;
+    const int ext[4] = {h->lay.g.nxh, h->lay.g.ny, h->lay.g.nz, h->lay.g.nt};
+    for (int k = 0; k < 4; ++k) {
+        a.tshape[k] = h->tshape[k];
+        a.tcount[k] = h->tshape[0] ? (ext[k] + h->tshape[k] - 1) / h->tshape[k] : 1;
+    }
+    a.nyb = 1;
+    a.zslab = 1;
+    if (a.tile_order == 0) {
+        // z-slabs per XCD need whole work-groups per z-plane and 8 | Nz
+        const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
+        if (!h->tshape[0] && plane % h->block == 0 && h->lay.g.nz % 8 == 0) {
+            a.nyb = (int)(plane / h->block);
+            a.zslab = h->lay.g.nz / 8;
+        } else {
+            a.tile_order = 1;
+        }
+    }
     return a;
 }
 
@@ -383,8 +401,17 @@ int check_opts(const lat_options* o) {
     if (o->nhit < 1 || o->nhit > 127) return fail(LAT_EINVAL, "nhit must be in 1..127");
     if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 && o->block_size != 256)
         return fail(LAT_EINVAL, "block_size must be 0, 64, 128 or 256");
-    if (o->tile_order < 0 || o->tile_order > 2) return fail(LAT_EINVAL, "tile_order must be 0, 1 or 2");
+    if (o->tile_order < 0 || o->tile_order > 3) return fail(LAT_EINVAL, "tile_order must be 0..3");
     if (o->layout < 0 || o->layout > 1) return fail(LAT_EINVAL, "layout must be 0 or 1");
+    if (o->tile[0] || o->tile[1] || o->tile[2] || o->tile[3]) {
+        long prod = 1;
+        for (int k = 0; k < 4; ++k) {
+            if (o->tile[k] < 1 || o->tile[k] > 256) return fail(LAT_EINVAL, "tile extents must be 1..256");
+            prod *= o->tile[k];
+        }
+        if (prod != 64 && prod != 128 && prod != 256) return fail(LAT_EINVAL, "tile must hold 64, 128 or 256 sites");
+        if (o->block_size && o->block_size != prod) return fail(LAT_EINVAL, "block_size must equal the tile size");
+    }
     return LAT_OK;
 }
 
@@ -454,6 +481,10 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     h->lat_id = o.lattice_id;
     h->block = o.block_size ? o.block_size : 256;
     h->tile_order = o.tile_order;
+    if (o.tile[0]) {
+        for (int k = 0; k < 4; ++k) h->tshape[k] = o.tile[k];
+        h->block = o.tile[0] * o.tile[1] * o.tile[2] * o.tile[3];
+    }
     h->dims[0] = Nx;
     h->dims[1] = Ny;
     h->dims[2] = Nz;

@@ -14,18 +14,62 @@
 
 using namespace latdev;
 
+#define LAT_HOST_DEV_INLINE static inline
+
 namespace {
 
-// Block -> tile map.  The dispatcher hands block b to XCD b % 8; the
-// XCD-aware order gives every XCD one contiguous range of tiles so that the
-// y/z/t neighbours a tile reads are mostly in that XCD's own L2.
-LAT_DEV int64_t tile_index(int order) {
+// Block -> tile map.  The dispatcher hands block b to XCD b % 8 (each XCD
+// has its own L2).  order 0: XCD k owns the z-slab [k*zslab, (k+1)*zslab) for
+// every t, so neighbours in x, y and t stay in its L2 and z crosses only at
+// the slab faces (the host falls back to order 1 when 8 does not divide Nz
+// or work-groups do not tile whole z-planes); 1: identity; 2: reversed;
+// 3: one contiguous range of tiles per XCD.
+LAT_DEV int64_t tile_index(int order, int nyb = 1, int zslab = 1, int nz = 1) {
     const int64_t nb = gridDim.x, b = blockIdx.x;
     if (order == 1) return b;
     if (order == 2) return nb - 1 - b;
+    if (order == 0) {
+        const int k = (int)(b & 7);
+        int64_t j = b >> 3;
+        const int yb = (int)(j % nyb);
+        j /= nyb;
+        const int zl = (int)(j % zslab);
+        const int64_t t = j / zslab;
+        return yb + (int64_t)nyb * ((k * zslab + zl) + (int64_t)nz * t);
+    }
     const int64_t x = b & 7, k = b >> 3;
     const int64_t per = nb >> 3, rem = nb & 7;
     return x * per + (x < rem ? x : rem) + k;
+}
+
+// Half-lattice index of this thread's site, or -1 if it lies outside the
+// lattice.  Lexicographic runs of blockDim sites, or a compact 4-D tile
+// (x/2, y, z, t) per work-group so that neighbour links are shared inside
+// the work-group and its XCD.
+LAT_DEV int64_t thread_site(const PassArgs& a) {
+    const int64_t tile = tile_index(a.tile_order, a.nyb, a.zslab, a.g.nz);
+    if (a.tshape[0] == 0) {
+        const int64_t s = tile * (int64_t)blockDim.x + threadIdx.x;
+        return s < a.g.vh ? s : -1;
+    }
+    int64_t r = tile;
+    const int bx = (int)(r % a.tcount[0]);
+    r /= a.tcount[0];
+    const int by = (int)(r % a.tcount[1]);
+    r /= a.tcount[1];
+    const int bz = (int)(r % a.tcount[2]);
+    const int bt = (int)(r / a.tcount[2]);
+    int i = threadIdx.x;
+    const int ix = i % a.tshape[0];
+    i /= a.tshape[0];
+    const int iy = i % a.tshape[1];
+    i /= a.tshape[1];
+    const int iz = i % a.tshape[2];
+    const int it = i / a.tshape[2];
+    const int xh = bx * a.tshape[0] + ix, y = by * a.tshape[1] + iy;
+    const int z = bz * a.tshape[2] + iz, t = bt * a.tshape[3] + it;
+    if (xh >= a.g.nxh || y >= a.g.ny || z >= a.g.nz || t >= a.g.nt) return -1;
+    return xh + (int64_t)a.g.nxh * (y + (int64_t)a.g.ny * (z + (int64_t)a.g.nz * t));
 }
 
 constexpr int SUB_A[3] = {0, 1, 0};
@@ -48,6 +92,8 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
 
     // staple A = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
     //                           + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)]
+    // The six links of one direction nu are requested together, so that the
+    // neighbouring threads that reuse them find the lines still in L2.
     M A = zero3<T>();
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
@@ -55,16 +101,15 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
         const int64_t s_pn = half_index(a.g, step(a.g, c, nu, +1));
         const int64_t s_mn = half_index(a.g, step(a.g, c, nu, -1));
         const int64_t s_pmmn = half_index(a.g, step(a.g, cpm, nu, -1));
-        {
-            M t = mul_na(load_link<ST>(L, vp, q, nu, s_pm), load_link<ST>(L, vp, q, mu, s_pn));
-            acc3(A, mul_na(t, load_link<ST>(L, vp, p, nu, s)));
-        }
-        {
-            M t = mul_nn(load_link<ST>(L, vp, q, mu, s_mn), load_link<ST>(L, vp, p, nu, s_pmmn));
-            acc3(A, mul_an(t, load_link<ST>(L, vp, q, nu, s_mn)));
-        }
+        const M f0 = load_link<ST>(L, vp, q, nu, s_pm);
+        const M f1 = load_link<ST>(L, vp, q, mu, s_pn);
+        const M f2 = load_link<ST>(L, vp, p, nu, s);
+        const M b0 = load_link<ST>(L, vp, q, mu, s_mn);
+        const M b1 = load_link<ST>(L, vp, p, nu, s_pmmn);
+        const M b2 = load_link<ST>(L, vp, q, nu, s_mn);
+        acc3(A, mul_na(mul_na(f0, f1), f2));
+        acc3(A, mul_an(mul_nn(b0, b1), b2));
     }
-
     M U = load_link<ST>(L, vp, p, mu, s);
     M W = mul_nn(U, A);  // link times staple: the local action is Re Tr(W)
 
@@ -132,8 +177,8 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
 
 template <class ST, int KIND, bool REUNIT, int RNG>
 __global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
-    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
-    if (s < a.g.vh) su3_site<ST, KIND, REUNIT, RNG>(a, s);
+    const int64_t s = thread_site(a);
+    if (s >= 0) su3_site<ST, KIND, REUNIT, RNG>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,8 +269,8 @@ LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
 
 template <class ST, int KIND, bool REUNIT, int RNG>
 __global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
-    const int64_t s = tile_index(a.tile_order) * (int64_t)blockDim.x + threadIdx.x;
-    if (s < a.g.vh) su2_site<ST, KIND, REUNIT, RNG>(a, s);
+    const int64_t s = thread_site(a);
+    if (s >= 0) su2_site<ST, KIND, REUNIT, RNG>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -658,6 +703,9 @@ LAT_DEV void batch_tile(const BatchArgs& b, int m, int tile, int64_t gp) {
     a.hb_offset = sweep * b.n_hb + (kind == 0 ? sw : 0);
     a.tile_order = 1;
     a.flux = L.flux;
+    a.tshape[0] = a.tshape[1] = a.tshape[2] = a.tshape[3] = 0;
+    a.tcount[0] = a.tcount[1] = a.tcount[2] = a.tcount[3] = 1;
+    a.nyb = a.zslab = 1;
     const int64_t end = (int64_t)(tile + 1) * b.tile < L.g.vh ? (int64_t)(tile + 1) * b.tile : L.g.vh;
     for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < end; s += blockDim.x)
         batch_site<ST3, ST2>(a, kind, reunit, s);
@@ -721,15 +769,20 @@ __global__ void batch_bump(BatchArgs b, uint64_t** counters, int n) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+LAT_HOST_DEV_INLINE unsigned pass_blocks(const PassArgs& a, int block) {
+    if (a.tshape[0]) return (unsigned)a.tcount[0] * a.tcount[1] * a.tcount[2] * a.tcount[3];
+    return (unsigned)((a.g.vh + block - 1) / block);
+}
+
 template <class ST, int KIND, bool RE, int RNG>
 hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
-    const unsigned nb = (unsigned)((a.g.vh + block - 1) / block);
+    const unsigned nb = pass_blocks(a, block);
     hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), 0, st, a);
     return hipGetLastError();
 }
 template <class ST, int KIND, bool RE, int RNG>
 hipError_t launch_su2(const PassArgs& a, int block, hipStream_t st) {
-    const unsigned nb = (unsigned)((a.g.vh + block - 1) / block);
+    const unsigned nb = pass_blocks(a, block);
     hipLaunchKernelGGL((su2_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), 0, st, a);
     return hipGetLastError();
 }

@@ -33,6 +33,9 @@ struct PassArgs {
     int hb_offset;         // index of this heat-bath sweep within the compound sweep
     int tile_order;        // 0 XCD-aware, 1 identity, 2 reversed
     int flux;
+    int tshape[4];         // work-group tile (x/2, y, z, t) in sites of one parity; 0 = lexicographic runs
+    int tcount[4];         // tiles per direction
+    int nyb, zslab;        // z-slab order: work-groups per z-plane, z-planes per XCD
 };
 
 // Initialisation of one lattice.

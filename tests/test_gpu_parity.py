@@ -241,9 +241,12 @@ def test_unitarity_after_many_sweeps():
 
 
 def test_tile_order_independence_and_repeatability():
+    # z-slab per XCD (order 0 with 8 | Nz), identity, reversed, contiguous
+    # chunks, compact 4-D work-group tiles: the pass is order independent
     res = []
-    for order in (0, 1, 2, 0):
-        g = P.Lattice(3, (8, 8, 8, 8), 5.9, seed=17, tile_order=order)
+    for order, tile in ((0, None), (1, None), (2, None), (3, None), (0, (8, 4, 2, 1)), (1, (4, 4, 4, 4)), (0, None)):
+        g = P.Lattice(3, (16, 16, 16, 4), 5.9, seed=17, tile_order=order, block_size=64 if tile is None else 0,
+                      tile=tile)
         g.sweep(1, 2)
         res.append(g.get_links())
     for r in res[1:]:
