@@ -96,6 +96,9 @@ typedef struct {
     int tile[4];         /* sites of one parity per work-group as a 4-D tile
                             (x/2, y, z, t), product 64, 128 or 256; all 0 =
                             runs of block_size consecutive sites (default) */
+    int max_waves_per_simd; /* occupancy cap of the sweep kernels: 0 = default for
+                            the form (1 for SU(3) FP64, whose staple traffic then
+                            fits the L2 better; none otherwise), -1 = none, 1..8 */
 } lat_options;
 
 /* Fills *opt with the defaults listed above. */

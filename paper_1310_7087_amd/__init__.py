@@ -46,6 +46,7 @@ class Options(ctypes.Structure):
         ("tile_order", ctypes.c_int),
         ("layout", ctypes.c_int),
         ("tile", ctypes.c_int * 4),
+        ("max_waves_per_simd", ctypes.c_int),
     ]
 
 
@@ -126,7 +127,7 @@ def default_options() -> Options:
 
 def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, nhit=10,
                  lattice_id=0, stream=None, device_buffer=None, block_size=0, tile_order=0,
-                 layout=0, tile=None) -> Options:
+                 layout=0, tile=None, max_waves_per_simd=0) -> Options:
     o = default_options()
     o.storage = storage
     o.rng = rng
@@ -138,6 +139,7 @@ def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, 
     o.block_size = block_size
     o.tile_order = tile_order
     o.layout = layout
+    o.max_waves_per_simd = max_waves_per_simd
     if tile is not None:
         for k in range(4):
             o.tile[k] = int(tile[k])

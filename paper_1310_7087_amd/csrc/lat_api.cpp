@@ -140,6 +140,9 @@ int make_layout(int group, const int d[4], int storage, int rng, int layout, Lay
         lines += (17 - lines % 64 + 64) % 64;
         g.vh_pad = lines * per_line;
     }
+    // per-thread addresses are 32-bit byte offsets within one plane
+    if ((uint64_t)g.vh_pad * vec_bytes(group, storage) >= (1ull << 32))
+        return fail(LAT_EINVAL, "lattice too large for 32-bit plane offsets");
     L.g = g;
     L.links_off = 0;
     L.links_bytes = (size_t)g.vh_pad * 2 * 4 * bytes_per_link(group, storage);
@@ -181,6 +184,7 @@ struct lat_ctx {
     int block = 256;
     int tile_order = 0;
     int tshape[4] = {0, 0, 0, 0};
+    int lds_reserve = 0;  // caps the waves per SIMD of the pass kernels
     uint64_t hb_sweeps = 0, sweeps = 0;
     bool log_on = false;
     int8_t* accept_log = nullptr;
@@ -234,6 +238,7 @@ PassArgs pass_args(const lat_ctx* h) {
     }
     a.nyb = 1;
     a.zslab = 1;
+    a.lds_reserve = h->lds_reserve;
     if (a.tile_order == 0) {
         // z-slabs per XCD need whole work-groups per z-plane and 8 | Nz
         const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
@@ -333,6 +338,23 @@ int enqueue_measure(lat_ctx* h, bool series) {
     return LAT_OK;
 }
 
+// Dynamic LDS per work-group that lets at most `cap` waves per SIMD of a
+// `block`-thread work-group reside on a compute unit; 0 if it cannot be done.
+int occupancy_lds(int cap, int block) {
+    int dev = 0, per_cu = 0, per_block = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    const int waves_per_block = (block + 63) / 64;
+    const int bpc = (cap * 4) / waves_per_block;  // work-groups per CU wanted
+    if (bpc < 1 || per_cu <= 0) return 0;
+    int lds = per_cu / (bpc + 1) + 1;             // one more would not fit
+    lds = (lds + 1023) & ~1023;
+    if (lds > per_cu / bpc || lds > per_block) return 0;
+    return lds;
+}
+
 uint64_t time_seed() {
     uint64_t t = (uint64_t)std::chrono::high_resolution_clock::now().time_since_epoch().count();
     t ^= t >> 29;
@@ -403,6 +425,7 @@ int check_opts(const lat_options* o) {
         return fail(LAT_EINVAL, "block_size must be 0, 64, 128 or 256");
     if (o->tile_order < 0 || o->tile_order > 3) return fail(LAT_EINVAL, "tile_order must be 0..3");
     if (o->layout < 0 || o->layout > 1) return fail(LAT_EINVAL, "layout must be 0 or 1");
+    if (o->max_waves_per_simd < -1 || o->max_waves_per_simd > 8) return fail(LAT_EINVAL, "max_waves_per_simd -1..8");
     if (o->tile[0] || o->tile[1] || o->tile[2] || o->tile[3]) {
         long prod = 1;
         for (int k = 0; k < 4; ++k) {
@@ -481,6 +504,9 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     h->lat_id = o.lattice_id;
     h->block = o.block_size ? o.block_size : 256;
     h->tile_order = o.tile_order;
+    int cap = o.max_waves_per_simd;
+    if (cap == 0) cap = (group == 3 && o.storage == LAT_F64) ? 1 : -1;
+    h->lds_reserve = cap > 0 ? -cap : 0;  // resolved once the work-group size is known
     if (o.tile[0]) {
         for (int k = 0; k < 4; ++k) h->tshape[k] = o.tile[k];
         h->block = o.tile[0] * o.tile[1] * o.tile[2] * o.tile[3];
@@ -504,6 +530,7 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
         return fail(LAT_EINVAL, "MRG32k3a seed must be in [1, 4294944443)");
     }
     h->seed = seed;
+    if (h->lds_reserve < 0) h->lds_reserve = occupancy_lds(-h->lds_reserve, h->block);
     rc = init_handle(h, &o);
     if (rc) {
         std::string keep = g_err;

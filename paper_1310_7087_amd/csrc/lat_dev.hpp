@@ -48,6 +48,44 @@ LAT_DEV m3<T> zero3() {
         for (int j = 0; j < 3; ++j) r.e[i][j] = {T(0), T(0)};
     return r;
 }
+
+// Complex multiply-accumulate written as four fused multiply-adds per term
+// (without it the compiler keeps a separate multiply and add per product,
+// half again as many VALU instructions).
+LAT_DEV float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+LAT_DEV double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// s += a * b
+template <class T>
+LAT_DEV void cmac(cx<T>& s, cx<T> a, cx<T> b) {
+    s.re = fmad(a.re, b.re, s.re);
+    s.re = fmad(-a.im, b.im, s.re);
+    s.im = fmad(a.re, b.im, s.im);
+    s.im = fmad(a.im, b.re, s.im);
+}
+// s += a * conj(b)
+template <class T>
+LAT_DEV void cmacj(cx<T>& s, cx<T> a, cx<T> b) {
+    s.re = fmad(a.re, b.re, s.re);
+    s.re = fmad(a.im, b.im, s.re);
+    s.im = fmad(a.im, b.re, s.im);
+    s.im = fmad(-a.re, b.im, s.im);
+}
+// s += conj(a) * b
+template <class T>
+LAT_DEV void cjmac(cx<T>& s, cx<T> a, cx<T> b) {
+    s.re = fmad(a.re, b.re, s.re);
+    s.re = fmad(a.im, b.im, s.re);
+    s.im = fmad(a.re, b.im, s.im);
+    s.im = fmad(-a.im, b.re, s.im);
+}
+// first term of a sum: a * b
+template <class T>
+LAT_DEV cx<T> cmul0(cx<T> a, cx<T> b) { return {fmad(-a.im, b.im, a.re * b.re), fmad(a.im, b.re, a.re * b.im)}; }
+template <class T>
+LAT_DEV cx<T> cmulj0(cx<T> a, cx<T> b) { return {fmad(a.im, b.im, a.re * b.re), fmad(-a.re, b.im, a.im * b.re)}; }
+template <class T>
+LAT_DEV cx<T> cjmul0(cx<T> a, cx<T> b) { return {fmad(a.im, b.im, a.re * b.re), fmad(-a.im, b.re, a.re * b.im)}; }
+
 // A * B
 template <class T>
 LAT_DEV m3<T> mul_nn(const m3<T>& a, const m3<T>& b) {
@@ -56,9 +94,9 @@ LAT_DEV m3<T> mul_nn(const m3<T>& a, const m3<T>& b) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            cx<T> s = cmul(a.e[i][0], b.e[0][j]);
-            s = s + cmul(a.e[i][1], b.e[1][j]);
-            s = s + cmul(a.e[i][2], b.e[2][j]);
+            cx<T> s = cmul0(a.e[i][0], b.e[0][j]);
+            cmac(s, a.e[i][1], b.e[1][j]);
+            cmac(s, a.e[i][2], b.e[2][j]);
             r.e[i][j] = s;
         }
     return r;
@@ -71,9 +109,9 @@ LAT_DEV m3<T> mul_na(const m3<T>& a, const m3<T>& b) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            cx<T> s = cmulj(a.e[i][0], b.e[j][0]);
-            s = s + cmulj(a.e[i][1], b.e[j][1]);
-            s = s + cmulj(a.e[i][2], b.e[j][2]);
+            cx<T> s = cmulj0(a.e[i][0], b.e[j][0]);
+            cmacj(s, a.e[i][1], b.e[j][1]);
+            cmacj(s, a.e[i][2], b.e[j][2]);
             r.e[i][j] = s;
         }
     return r;
@@ -86,12 +124,32 @@ LAT_DEV m3<T> mul_an(const m3<T>& a, const m3<T>& b) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            cx<T> s = cjmul(a.e[0][i], b.e[0][j]);
-            s = s + cjmul(a.e[1][i], b.e[1][j]);
-            s = s + cjmul(a.e[2][i], b.e[2][j]);
+            cx<T> s = cjmul0(a.e[0][i], b.e[0][j]);
+            cjmac(s, a.e[1][i], b.e[1][j]);
+            cjmac(s, a.e[2][i], b.e[2][j]);
             r.e[i][j] = s;
         }
     return r;
+}
+// C += A * B^dagger
+template <class T>
+LAT_DEV void mac_na(m3<T>& c, const m3<T>& a, const m3<T>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cmacj(c.e[i][j], a.e[i][k], b.e[j][k]);
+}
+// C += A^dagger * B
+template <class T>
+LAT_DEV void mac_an(m3<T>& c, const m3<T>& a, const m3<T>& b) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) cjmac(c.e[i][j], a.e[k][i], b.e[k][j]);
 }
 template <class T>
 LAT_DEV void acc3(m3<T>& a, const m3<T>& b) {
@@ -129,10 +187,19 @@ LAT_DEV m3<To> cast3(const m3<From>& a) {
 }
 // row 3 = conj(row1 x row2): completes two orthonormal rows to det = 1
 template <class T>
+LAT_DEV cx<T> conj_cross(cx<T> a, cx<T> b, cx<T> c, cx<T> d) {  // conj(a b - c d)
+    cx<T> t = cmul0(a, b);
+    t.re = fmad(-c.re, d.re, t.re);
+    t.re = fmad(c.im, d.im, t.re);
+    t.im = fmad(-c.re, d.im, t.im);
+    t.im = fmad(-c.im, d.re, t.im);
+    return {t.re, -t.im};
+}
+template <class T>
 LAT_DEV void third_row(m3<T>& a) {
-    a.e[2][0] = conj(cmul(a.e[0][1], a.e[1][2]) - cmul(a.e[0][2], a.e[1][1]));
-    a.e[2][1] = conj(cmul(a.e[0][2], a.e[1][0]) - cmul(a.e[0][0], a.e[1][2]));
-    a.e[2][2] = conj(cmul(a.e[0][0], a.e[1][1]) - cmul(a.e[0][1], a.e[1][0]));
+    a.e[2][0] = conj_cross(a.e[0][1], a.e[1][2], a.e[0][2], a.e[1][1]);
+    a.e[2][1] = conj_cross(a.e[0][2], a.e[1][0], a.e[0][0], a.e[1][2]);
+    a.e[2][2] = conj_cross(a.e[0][0], a.e[1][1], a.e[0][1], a.e[1][0]);
 }
 // Gram-Schmidt on rows 1-2, then row 3 from the cross product (FP64)
 LAT_DEV void reunit3(m3<double>& a) {
@@ -353,25 +420,39 @@ LAT_DEV double bg_theta(const LatGeom& g, int flux, coord4 c, int mu) {
 // storage forms: each (parity, mu) holds NP planes of 8- or 16-byte vectors,
 // every plane a contiguous array over the padded half lattice.
 // ---------------------------------------------------------------------------
+// Element k of a link: plane k starts plane_bytes * k after the first plane;
+// the per-thread part of the address is a 32-bit byte offset (so the
+// uniform plane base stays in scalar registers).
+template <class V>
+LAT_DEV V ld_plane(const char* base, int64_t plane_bytes, int k, uint32_t off) {
+    return *reinterpret_cast<const V*>(base + k * plane_bytes + off);
+}
+template <class V>
+LAT_DEV void st_plane(char* base, int64_t plane_bytes, int k, uint32_t off, V v) {
+    *reinterpret_cast<V*>(base + k * plane_bytes + off) = v;
+}
+
 struct st_f64 {  // SU(3), 18 doubles: 9 planes of (re, im)
     using real = double;
     using mat = m3<double>;
     static constexpr int NP = 9;
     static constexpr int VB = 16;
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
-        const double2* p = reinterpret_cast<const double2*>(base) + s;
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
         mat m;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double2 v = p[k * plane_stride];
+            const double2 v = ld_plane<double2>(base, pb, k, off);
             m.e[k / 3][k % 3] = {v.x, v.y};
         }
         return m;
     }
     LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
-        double2* p = reinterpret_cast<double2*>(base) + s;
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) p[k * plane_stride] = make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+        for (int k = 0; k < 9; ++k) st_plane(base, pb, k, off, make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im));
     }
 };
 struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
@@ -380,19 +461,21 @@ struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
     static constexpr int NP = 9;
     static constexpr int VB = 8;
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
-        const float2* p = reinterpret_cast<const float2*>(base) + s;
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
         mat m;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            float2 v = p[k * plane_stride];
+            const float2 v = ld_plane<float2>(base, pb, k, off);
             m.e[k / 3][k % 3] = {v.x, v.y};
         }
         return m;
     }
     LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
-        float2* p = reinterpret_cast<float2*>(base) + s;
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) p[k * plane_stride] = make_float2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im);
+        for (int k = 0; k < 9; ++k) st_plane(base, pb, k, off, make_float2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im));
     }
 };
 struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
@@ -401,8 +484,11 @@ struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
     static constexpr int NP = 3;
     static constexpr int VB = 16;
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
-        const float4* p = reinterpret_cast<const float4*>(base) + s;
-        float4 a = p[0], b = p[plane_stride], c = p[2 * plane_stride];
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        const float4 a = ld_plane<float4>(base, pb, 0, off);
+        const float4 b = ld_plane<float4>(base, pb, 1, off);
+        const float4 c = ld_plane<float4>(base, pb, 2, off);
         mat m;
         m.e[0][0] = {a.x, a.y};
         m.e[0][1] = {a.z, a.w};
@@ -414,10 +500,11 @@ struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
         return m;
     }
     LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
-        float4* p = reinterpret_cast<float4*>(base) + s;
-        p[0] = make_float4(m.e[0][0].re, m.e[0][0].im, m.e[0][1].re, m.e[0][1].im);
-        p[plane_stride] = make_float4(m.e[0][2].re, m.e[0][2].im, m.e[1][0].re, m.e[1][0].im);
-        p[2 * plane_stride] = make_float4(m.e[1][1].re, m.e[1][1].im, m.e[1][2].re, m.e[1][2].im);
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        st_plane(base, pb, 0, off, make_float4(m.e[0][0].re, m.e[0][0].im, m.e[0][1].re, m.e[0][1].im));
+        st_plane(base, pb, 1, off, make_float4(m.e[0][2].re, m.e[0][2].im, m.e[1][0].re, m.e[1][0].im));
+        st_plane(base, pb, 2, off, make_float4(m.e[1][1].re, m.e[1][1].im, m.e[1][2].re, m.e[1][2].im));
     }
 };
 struct sq_f64 {  // SU(2), 4 doubles: 2 planes of double2
@@ -426,14 +513,16 @@ struct sq_f64 {  // SU(2), 4 doubles: 2 planes of double2
     static constexpr int NP = 2;
     static constexpr int VB = 16;
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
-        const double2* p = reinterpret_cast<const double2*>(base) + s;
-        double2 a = p[0], b = p[plane_stride];
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        const double2 a = ld_plane<double2>(base, pb, 0, off), b = ld_plane<double2>(base, pb, 1, off);
         return {a.x, a.y, b.x, b.y};
     }
     LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
-        double2* p = reinterpret_cast<double2*>(base) + s;
-        p[0] = make_double2(m.q0, m.q1);
-        p[plane_stride] = make_double2(m.q2, m.q3);
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        st_plane(base, pb, 0, off, make_double2(m.q0, m.q1));
+        st_plane(base, pb, 1, off, make_double2(m.q2, m.q3));
     }
 };
 struct sq_f32 {  // SU(2), 4 floats: 1 plane of float4
@@ -442,11 +531,11 @@ struct sq_f32 {  // SU(2), 4 floats: 1 plane of float4
     static constexpr int NP = 1;
     static constexpr int VB = 16;
     LAT_DEV static mat load(const char* base, int64_t, int64_t s) {
-        float4 a = reinterpret_cast<const float4*>(base)[s];
+        const float4 a = ld_plane<float4>(base, 0, 0, (uint32_t)s * VB);
         return {a.x, a.y, a.z, a.w};
     }
     LAT_DEV static void store(char* base, int64_t, int64_t s, const mat& m) {
-        reinterpret_cast<float4*>(base)[s] = make_float4(m.q0, m.q1, m.q2, m.q3);
+        st_plane(base, 0, 0, (uint32_t)s * VB, make_float4(m.q0, m.q1, m.q2, m.q3));
     }
 };
 

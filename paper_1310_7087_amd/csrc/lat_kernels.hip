@@ -107,8 +107,8 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
         const M b0 = load_link<ST>(L, vp, q, mu, s_mn);
         const M b1 = load_link<ST>(L, vp, p, nu, s_pmmn);
         const M b2 = load_link<ST>(L, vp, q, nu, s_mn);
-        acc3(A, mul_na(mul_na(f0, f1), f2));
-        acc3(A, mul_an(mul_nn(b0, b1), b2));
+        mac_na(A, mul_na(f0, f1), f2);
+        mac_an(A, mul_nn(b0, b1), b2);
     }
     M U = load_link<ST>(L, vp, p, mu, s);
     M W = mul_nn(U, A);  // link times staple: the local action is Re Tr(W)
@@ -706,6 +706,7 @@ LAT_DEV void batch_tile(const BatchArgs& b, int m, int tile, int64_t gp) {
     a.tshape[0] = a.tshape[1] = a.tshape[2] = a.tshape[3] = 0;
     a.tcount[0] = a.tcount[1] = a.tcount[2] = a.tcount[3] = 1;
     a.nyb = a.zslab = 1;
+    a.lds_reserve = 0;
     const int64_t end = (int64_t)(tile + 1) * b.tile < L.g.vh ? (int64_t)(tile + 1) * b.tile : L.g.vh;
     for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < end; s += blockDim.x)
         batch_site<ST3, ST2>(a, kind, reunit, s);
@@ -777,13 +778,13 @@ LAT_HOST_DEV_INLINE unsigned pass_blocks(const PassArgs& a, int block) {
 template <class ST, int KIND, bool RE, int RNG>
 hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
     const unsigned nb = pass_blocks(a, block);
-    hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), a.lds_reserve, st, a);
     return hipGetLastError();
 }
 template <class ST, int KIND, bool RE, int RNG>
 hipError_t launch_su2(const PassArgs& a, int block, hipStream_t st) {
     const unsigned nb = pass_blocks(a, block);
-    hipLaunchKernelGGL((su2_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), 0, st, a);
+    hipLaunchKernelGGL((su2_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), a.lds_reserve, st, a);
     return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ struct PassArgs {
     int tshape[4];         // work-group tile (x/2, y, z, t) in sites of one parity; 0 = lexicographic runs
     int tcount[4];         // tiles per direction
     int nyb, zslab;        // z-slab order: work-groups per z-plane, z-planes per XCD
+    int lds_reserve;       // dynamic LDS bytes reserved per work-group (caps occupancy)
 };
 
 // Initialisation of one lattice.
