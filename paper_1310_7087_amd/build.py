@@ -20,6 +20,9 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["lat_kernels.hip", "lat_api.cpp"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # no implicit contraction: fused multiply-adds are written out where
+    # wanted, so every kernel that inlines the same update rounds the same way
+    "-ffp-contract=off",
     # packed-FP32 instructions are disabled: the compiler must not form them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -374,6 +374,57 @@ LAT_DEV int kp(double alpha, int nhit, DR& d, int g, qt<double>& x) {
     return -1;
 }
 
+// First try of a KP draw and the direction of the SU(2) element, prepared
+// from the random numbers alone (they do not depend on the links): the
+// transcendental work then overlaps the staple's memory traffic.  Only for
+// counter-addressed or constant generators, whose draws do not depend on how
+// many tries earlier subgroups took.
+struct kp_first {
+    double num;             // ln R1 + cos^2(2 pi R2) ln R3 of try 0
+    double r4sq;            // R4^2 of try 0
+    double dx, dy, dz;      // unit direction of (a1, a2, a3)
+};
+template <class DR>
+LAT_DEV kp_first kp_prepare(DR& d, int g) {
+    kp_first f;
+    double R[4], D[2];
+    d.try4(g, 0, R);
+    const double c = cos(TWO_PI * R[1]);
+    f.num = log(R[0]) + c * c * log(R[2]);
+    f.r4sq = R[3] * R[3];
+    d.dir2(g, D);
+    const double ct = 2.0 * D[0] - 1.0;
+    const double st = sqrt(1.0 - ct * ct);
+    double sp, cp;
+    sincos(TWO_PI * D[1], &sp, &cp);
+    f.dx = st * cp;
+    f.dy = st * sp;
+    f.dz = ct;
+    return f;
+}
+// The same draw as kp(), starting from a prepared first try.
+template <class DR>
+LAT_DEV int kp_prepared(double alpha, int nhit, DR& d, int g, const kp_first& f, qt<double>& x) {
+    double lam2 = -f.num / (2.0 * alpha);
+    int t = 0;
+    if (!(f.r4sq <= 1.0 - lam2)) {
+        for (t = 1; t < nhit; ++t) {
+            double R[4];
+            d.try4(g, t, R);
+            const double c = cos(TWO_PI * R[1]);
+            lam2 = -(log(R[0]) + c * c * log(R[2])) / (2.0 * alpha);
+            if (R[3] * R[3] <= 1.0 - lam2) break;
+        }
+        if (t == nhit) {
+            x = {1.0, 0.0, 0.0, 0.0};
+            return -1;
+        }
+    }
+    const double s = 2.0 * sqrt(lam2 * (1.0 - lam2));
+    x = {1.0 - 2.0 * lam2, s * f.dx, s * f.dy, s * f.dz};
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // geometry of the parity-split layout
 // ---------------------------------------------------------------------------

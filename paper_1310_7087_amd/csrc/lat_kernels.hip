@@ -90,6 +90,31 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     const coord4 cpm = step(a.g, c, mu, +1);
     const int64_t s_pm = half_index(a.g, cpm);
 
+    int64_t canon = 0;
+    draws<RNG> d;
+    if constexpr (KIND == 0) {
+        canon = canon_index(a.g, c);
+        if constexpr (RNG == LAT_RNG_PHILOX_I) {
+            d.site = (uint32_t)canon;
+            d.lat = a.lat_id;
+            d.word2 = (uint32_t)(4 * (*a.hb_count + (uint64_t)a.hb_offset) + mu);
+            d.k0 = a.key0;
+            d.k1 = a.key1;
+            d.nhit = a.nhit;
+        } else if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+            for (int w = 0; w < 6; ++w) d.st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+        } else {
+            d.c = a.rng_const;
+        }
+    }
+    constexpr bool PREPARE = (KIND == 0 && RNG != LAT_RNG_MRG_I);
+    kp_first first[3];
+    if constexpr (PREPARE) {
+#pragma unroll
+        for (int g = 0; g < 3; ++g) first[g] = kp_prepare(d, g);
+    }
+
     // staple A = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
     //                           + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)]
     // The six links of one direction nu are requested together, so that the
@@ -113,25 +138,6 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     M U = load_link<ST>(L, vp, p, mu, s);
     M W = mul_nn(U, A);  // link times staple: the local action is Re Tr(W)
 
-    int64_t canon = 0;
-    draws<RNG> d;
-    if constexpr (KIND == 0) {
-        canon = canon_index(a.g, c);
-        if constexpr (RNG == LAT_RNG_PHILOX_I) {
-            d.site = (uint32_t)canon;
-            d.lat = a.lat_id;
-            d.word2 = (uint32_t)(4 * (*a.hb_count + (uint64_t)a.hb_offset) + mu);
-            d.k0 = a.key0;
-            d.k1 = a.key1;
-            d.nhit = a.nhit;
-        } else if constexpr (RNG == LAT_RNG_MRG_I) {
-#pragma unroll
-            for (int w = 0; w < 6; ++w) d.st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
-        } else {
-            d.c = a.rng_const;
-        }
-    }
-
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         const int ia = SUB_A[g], ib = SUB_B[g];
@@ -147,7 +153,9 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
                 continue;
             }
             qt<double> x;
-            const int t = kp(alpha, a.nhit, d, g, x);
+            int t;
+            if constexpr (PREPARE) t = kp_prepared(alpha, a.nhit, d, g, first[g], x);
+            else t = kp(alpha, a.nhit, d, g, x);
             if (log) *log = (int8_t)t;
             if (t < 0) continue;
             const double ik = 1.0 / k;
@@ -412,12 +420,25 @@ LAT_DEV void block_reduce_store(double (&v)[NV], double* out, int64_t stride, in
     }
 }
 
+// Work-group -> (tile, parity) of the plaquette sum: both parities of a
+// tile run on the same XCD (blocks b and b+8) right after each other, so the
+// links one parity reads as neighbours are still in L2 for the other.  The
+// grid is padded to whole groups of 16; padding blocks contribute nothing.
+LAT_DEV void plaq_block(int nb, int& tile, int& parity) {
+    const int b = blockIdx.x;
+    tile = ((b >> 4) << 3) | (b & 7);
+    parity = (b >> 3) & 1;
+    if (tile >= nb) tile = -1;
+}
+
 template <class ST>
 __global__ void __launch_bounds__(256) su3_plaq(MeasArgs a) {
     using T = typename ST::real;
     using M = m3<T>;
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int p = blockIdx.y, q = 1 - p;
+    int tile, p;
+    plaq_block(a.nb_plaq, tile, p);
+    const int q = 1 - p;
+    const int64_t s = tile < 0 ? a.g.vh : tile * (int64_t)blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (s < a.g.vh) {
         const int64_t vp = a.g.vh_pad;
@@ -437,15 +458,17 @@ __global__ void __launch_bounds__(256) su3_plaq(MeasArgs a) {
             }
         }
     }
-    block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + blockIdx.x);
+    if (tile >= 0) block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + tile);
 }
 
 template <class ST>
 __global__ void __launch_bounds__(256) su2_plaq(MeasArgs a) {
     using T = typename ST::real;
     using Q = qt<T>;
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int p = blockIdx.y, q = 1 - p;
+    int tile, p;
+    plaq_block(a.nb_plaq, tile, p);
+    const int q = 1 - p;
+    const int64_t s = tile < 0 ? a.g.vh : tile * (int64_t)blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (s < a.g.vh) {
         const int64_t vp = a.g.vh_pad;
@@ -465,7 +488,7 @@ __global__ void __launch_bounds__(256) su2_plaq(MeasArgs a) {
             }
         }
     }
-    block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + blockIdx.x);
+    if (tile >= 0) block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + tile);
 }
 
 template <class ST>
@@ -861,7 +884,7 @@ hipError_t lat_launch_init(int group, int storage, int rng, const InitArgs& a, h
 
 template <class ST, bool SU3>
 static hipError_t meas_dispatch(const MeasArgs& a, double* out, uint32_t* slot, hipStream_t st) {
-    dim3 gp((unsigned)a.nb_plaq, 2);
+    dim3 gp((unsigned)(16 * ((a.nb_plaq + 7) / 8)));
     dim3 gl((unsigned)a.nb_poly);
     if constexpr (SU3) {
         hipLaunchKernelGGL((su3_plaq<ST>), gp, dim3(256), 0, st, a);

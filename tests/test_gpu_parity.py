@@ -141,8 +141,8 @@ def test_su3_16x4_thermalised_compound_sweep():
 
 def test_su3_16x4_long_run_statistics():
     """100 (1 HB + 4 OR) sweeps from the Haar start; the chains decorrelate, so
-    the mean plaquette and Polyakov loop of sweeps 21..100 are compared
-    within their binned errors."""
+    the mean plaquettes and Polyakov-loop modulus of sweeps 21..100 are
+    compared within their binned errors."""
     w = SU3_16x4
     g, o = pair(w.group, w.dims, w.beta, seed=w.seed, start=O.HOT)
     pg, lg = g.run(100, 1, 4, measure_every=1)
@@ -157,7 +157,11 @@ def test_su3_16x4_long_run_statistics():
     def mean_err(x, nb=8):
         b = x[20:20 + (len(x) - 20) // nb * nb].reshape(nb, -1).mean(axis=1)
         return b.mean(), b.std(ddof=1) / np.sqrt(nb)
-    for a, b in ((pg[:, 0], po[:, 0]), (pg[:, 1], po[:, 1]), (pg[:, 2], po[:, 2]), (lg[:, 0], lo[:, 0])):
+    # beta 5.69 at Nt = 4 sits at the deconfinement point: Re L hops between
+    # centre sectors far slower than the bins, so the modulus |L| is compared
+    absg = np.hypot(lg[:, 0], lg[:, 1])
+    abso = np.hypot(lo[:, 0], lo[:, 1])
+    for a, b in ((pg[:, 0], po[:, 0]), (pg[:, 1], po[:, 1]), (pg[:, 2], po[:, 2]), (absg, abso)):
         (ma, ea), (mb, eb) = mean_err(a), mean_err(b)
         assert abs(ma - mb) < 4 * np.hypot(ea, eb) + 1e-6, (ma, ea, mb, eb)
 
