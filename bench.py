@@ -6,11 +6,16 @@ A step is one working sweep of the whole hot path on SU(3) 32^3 x 8
 compound sweep (1 heat-bath + 4 overrelaxation sweeps, reunitarisation
 fused into the last) followed by the plaquette and Polyakov-loop
 measurement.  The metric is link updates per second,
-steps * (1 + 4) * 4 V / time, with the lattice resident in HBM.
+steps * (1 + 4) * 4 V / time, with the lattice resident in HBM; the plain
+FP64 18-real form gives the headline value.  Each form first picks its
+launch shape with the library's autotuner (the lattice state is restored).
 
-Also reported: the FP32 and 12-real FP32 storage forms, the per-kernel
-roofline of the dominant pass kernel (event-timed in this run), and the FP64
-CPU oracle timed on a bounded sample of the same workload on the host cores.
+Also reported: the FP32 and 12-real FP32 storage forms (speed-up over FP64
+and the difference of their mean plaquette from the FP64 one), the roofline
+of the dominant pass kernel (event-timed in this run), SU(3) 64^3 x 16 (the
+case that does not fit the last-level cache), the 64-lattice batch in FP32
+against the same lattices run one by one in FP64, and the FP64 CPU oracle
+timed on a bounded sample of the headline workload on the host cores.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -23,8 +28,9 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-if ROOT not in sys.path:
-    sys.path.insert(0, ROOT)
+for p in (ROOT, os.path.join(ROOT, "tests")):
+    if p not in sys.path:
+        sys.path.insert(0, p)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 DIMS = (32, 32, 32, 8)
@@ -48,15 +54,35 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def volume(dims) -> int:
+    v = 1
+    for d in dims:
+        v *= int(d)
+    return v
+
+
+def binned(x, nbins=10):
+    """Mean and binned standard error of a series (last nbins*k entries)."""
+    import numpy as np
+    x = np.asarray(x, dtype=float)
+    n = len(x) // nbins * nbins
+    if n < 2 * nbins:
+        return float(np.mean(x)), float("nan")
+    b = x[len(x) - n:].reshape(nbins, -1).mean(axis=1)
+    return float(b.mean()), float(b.std(ddof=1) / np.sqrt(nbins))
+
+
+def storage_of(P, form):
+    return {"f64": P.F64, "f32": P.F32, "f32c12": P.F32_C12}[form]
+
+
 def run_form(P, form: str, steps: int, warmup: int):
-    storage = {"f64": P.F64, "f32": P.F32, "f32c12": P.F32_C12}[form]
-    V = 1
-    for d in DIMS:
-        V *= d
-    lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage, rng=P.RNG_PHILOX, seed=3, start=P.COLD)
-    log(f"[{form}] warmup {warmup} steps")
-    lat.run(warmup, N_HB, N_OR, measure_every=1)
     import torch
+    V = volume(DIMS)
+    lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=3, start=P.COLD)
+    shape = lat.autotune(N_HB, N_OR)
+    log(f"[{form}] launch shape {shape}; warmup {warmup} steps")
+    lat.run(warmup, N_HB, N_OR, measure_every=1)
     torch.cuda.synchronize()
     log(f"[{form}] timing {steps} steps")
     t0 = time.perf_counter()
@@ -65,13 +91,17 @@ def run_form(P, form: str, steps: int, warmup: int):
     dt = time.perf_counter() - t0
     updates = steps * (N_HB + N_OR) * 4 * V
     # event-timed passes of the same kernels on the same stream
-    t_hb, t_or = lat.profile_passes(N_HB, N_OR, reps=3)
+    t_hb, t_or = lat.profile_passes(N_HB, N_OR, reps=5)
     b = BYTES_PER_LINK[form]
     pass_bytes = 4.5 * V * b  # reads all 4V links, writes the V/2 updated ones
+    p_mean, p_err = binned(plaq[:, 0])
     res = {
         "link_updates_per_s": updates / dt,
         "ms_per_step": 1e3 * dt / steps,
-        "plaquette_last": float(plaq[-1][0]),
+        "launch_shape": shape,
+        "plaquette_mean": p_mean,
+        "plaquette_err": p_err,
+        "plaquette_last": [float(x) for x in plaq[-1]],
         "polyakov_last": [float(poly[-1][0]), float(poly[-1][1])],
         "hb_pass_us": 1e3 * t_hb,
         "or_pass_us": 1e3 * t_or,
@@ -85,13 +115,76 @@ def run_form(P, form: str, steps: int, warmup: int):
     return res
 
 
-def cpu_baseline(steps: int = 1):
+def run_large(P, sweeps: int = 40):
+    """SU(3) 64^3 x 16, beta 6.0, Haar start (seed 23): FP64 18-real against
+    FP32 12-real on the lattice that does not fit the 256 MB last-level cache."""
+    dims = (64, 64, 64, 16)
+    V = volume(dims)
+    out = {}
+    for form in ("f64", "f32c12"):
+        lat = P.Lattice(3, dims, 6.0, 0, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=23, start=P.HOT)
+        shape = lat.autotune(N_HB, N_OR)
+        t0 = time.perf_counter()
+        plaq, _ = lat.run(sweeps, N_HB, N_OR, measure_every=1)
+        dt = time.perf_counter() - t0
+        t_hb, t_or = lat.profile_passes(N_HB, N_OR, reps=2)
+        b = BYTES_PER_LINK[form]
+        r = {"launch_shape": shape, "link_updates_per_s": sweeps * 5 * 4 * V / dt,
+             "ms_per_step": 1e3 * dt / sweeps, "algorithmic_GBs": sweeps * 5 * 4 * V * 9 * b / dt / 1e9,
+             "or_pass_us": 1e3 * t_or, "hb_pass_us": 1e3 * t_hb,
+             "or_pass_hbm_fraction": 4.5 * V * b / (t_or * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "plaquette_tail": [float(x) for x in plaq[-3:, 0]]}
+        r["hbm_fraction"] = r["algorithmic_GBs"] / HBM_PEAK_GBS
+        r["plaquette_mean_last_half"], r["plaquette_err_last_half"] = binned(plaq[sweeps // 2:, 0], 5)
+        out[form] = r
+        lat.close()
+        log(f"[64^3x16 {form}] {r['link_updates_per_s']:.3e} link updates/s")
+    out["speedup_f32c12_vs_f64"] = out["f32c12"]["link_updates_per_s"] / out["f64"]["link_updates_per_s"]
+    out["delta_plaquette_f32c12_minus_f64"] = (out["f32c12"]["plaquette_mean_last_half"]
+                                              - out["f64"]["plaquette_mean_last_half"])
+    out["config"] = {"lattice": list(dims), "beta": 6.0, "start": "hot", "seed": 23, "sweeps": sweeps,
+                     "n_hb": N_HB, "n_or": N_OR}
+    return out
+
+
+def run_batch(P, sweeps: int = 10):
+    """64 independent lattices (SU(2)/SU(3), 8^3x4 .. 24^3x6, coupling scan):
+    the FP32 batch launch against the same lattices run one by one in FP64."""
+    from inputs import batch_workloads
+    ws = batch_workloads(64, seed=11)
+    descs = [dict(group=w.group, dims=w.dims, beta=w.beta, flux=w.flux, seed=w.seed, start=w.start,
+                  lattice_id=w.lattice_id) for w in ws]
+    links = sum(4 * volume(w.dims) for w in ws)
+    bt = P.Batch(descs, storage=P.F32)
+    shape = bt.autotune(N_HB, N_OR)
+    bt.run(2, N_HB, N_OR, measure=False)
+    t0 = time.perf_counter()
+    bt.run(sweeps, N_HB, N_OR, measure=False)
+    dt_b = time.perf_counter() - t0
+    bt.close()
+    singles = [P.Lattice(d["group"], d["dims"], d["beta"], 0, storage=P.F64, rng=P.RNG_PHILOX,
+                         seed=d["seed"], lattice_id=d["lattice_id"], start=d["start"]) for d in descs]
+    for s in singles:
+        s.run(2, N_HB, N_OR, measure_every=0)
+    t0 = time.perf_counter()
+    for s in singles:
+        s.run(sweeps, N_HB, N_OR, measure_every=0)
+    dt_s = time.perf_counter() - t0
+    for s in singles:
+        s.close()
+    r_b = sweeps * 5 * links / dt_b
+    r_s = sweeps * 5 * links / dt_s
+    log(f"[batch] F32 batched {r_b:.3e} vs F64 one by one {r_s:.3e} link updates/s")
+    return {"lattices": len(ws), "total_links": links, "sweeps": sweeps, "launch_shape": shape,
+            "f32_batched_link_updates_per_s": r_b, "f64_one_by_one_link_updates_per_s": r_s,
+            "speedup": r_b / r_s}
+
+
+def cpu_baseline(steps: int):
     import oracle as O
     cores = len(os.sched_getaffinity(0))
     O.set_threads(cores)
-    V = 1
-    for d in DIMS:
-        V *= d
+    V = volume(DIMS)
     ref = O.Lattice(3, DIMS, BETA, flux=FLUX, rng=O.RNG_PHILOX, seed=3, start=O.COLD)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -112,7 +205,8 @@ def traffic_for(kernel: str, form: str):
     if not os.path.exists(path):
         return None
     try:
-        data = json.load(open(path))
+        with open(path) as fh:
+            data = json.load(fh)
     except ValueError:
         return None
     if data.get("kernel_hash") != kernel_hash():
@@ -124,11 +218,12 @@ def traffic_for(kernel: str, form: str):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--forms", default="f64,f32,f32c12",
                     help="storage forms to time; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 64^3x16 and batch measurements")
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="steps of the CPU oracle in the bounded baseline sample (about 1 s each on 16 cores)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -162,9 +257,6 @@ def main() -> int:
             f"{results[f]['algorithmic_GBs']:.0f} GB/s algorithmic")
     head = forms[0]
     r = results[head]
-    V = 1
-    for d in DIMS:
-        V *= d
     # dominant kernel: the pass kind with the larger share of a compound sweep
     share_hb = N_HB * 8 * r["hb_pass_us"]
     share_or = N_OR * 8 * r["or_pass_us"]
@@ -198,7 +290,12 @@ def main() -> int:
     if "f64" in results:
         for f in forms:
             if f != "f64":
-                out["forms"][f]["speedup_vs_f64"] = results[f]["link_updates_per_s"] / results["f64"]["link_updates_per_s"]
+                fr = out["forms"][f]
+                fr["speedup_vs_f64"] = results[f]["link_updates_per_s"] / results["f64"]["link_updates_per_s"]
+                fr["delta_plaquette_vs_f64"] = results[f]["plaquette_mean"] - results["f64"]["plaquette_mean"]
+    if not args.no_extras:
+        out["su3_64x16"] = run_large(P)
+        out["batch_64_lattices"] = run_batch(P)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)

@@ -169,6 +169,20 @@ int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words);
  */
 int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, double* ms_or);
 
+/*
+ * Autotuner (the paper foresees auto-tuning of launch parameters from
+ * profiling, Sec. 6): times the sweep kernels with every candidate
+ * work-group size (64, 128, 256), work-group order (0, 1) and occupancy cap
+ * (none, 1, 2, 3 waves per SIMD) on compound sweeps (n_hb, n_or) of this
+ * lattice, keeps the fastest, and restores the lattice's device state and
+ * counters, so the Markov chain is unchanged (results do not depend on the
+ * shape).  If the environment variable LAT_TUNE_CACHE names a file, choices
+ * are read from and appended to it (key: group, extents, storage, device).
+ * result (optional) receives {work-group size, order, cap (-1 = none)}.
+ * Synchronises.  LAT_ESTATE with the accept log on or an explicit 4-D tile.
+ */
+int lat_autotune(lat_t h, int n_hb, int n_or, int result[3]);
+
 /* Any output pointer may be NULL. */
 int lat_get_info(lat_t h, uint64_t* seed_used, uint64_t* hb_sweeps_done, uint64_t* sweeps_done);
 
@@ -231,6 +245,12 @@ int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_optio
  * of the persistent kernel (0 = 1024 threads per compute unit).  Every form
  * and shape gives bit-identical results. */
 int lat_batch_configure(lat_batch_t b, int mode, int block_size, int sites_per_thread, int grid);
+/* Autotuner of the batch launch: times every work-group size (64, 128,
+ * 256) and sites per thread (1, 2, 4) on compound sweeps (n_hb, n_or) of
+ * the whole batch, keeps the fastest and restores every member's state
+ * (cache file as for lat_autotune).  result (optional) = {size, sites per
+ * thread}.  Synchronises. */
+int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[2]);
 /* n_sweeps compound sweeps of every member; if plaq / poly are non-NULL they
  * receive each member's final measurement ([n][3] and [n][2]); synchronises. */
 int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly);

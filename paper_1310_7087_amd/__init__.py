@@ -80,6 +80,7 @@ def _load():
     L.lat_get_rng_state.argtypes = [vp, vp, sz]
     L.lat_get_info.argtypes = [vp, P(u64), P(u64), P(u64)]
     L.lat_profile_passes.argtypes = [vp, i, i, i, P(d), P(d)]
+    L.lat_autotune.argtypes = [vp, i, i, vp]
     L.lat_set_accept_log.argtypes = [vp, i]
     L.lat_get_accept_log.argtypes = [vp, vp, sz]
     L.lat_get_accept_log.restype = i64
@@ -92,13 +93,15 @@ def _load():
     L.lat_batch_create.argtypes = [P(vp), i, P(Desc), P(Options)]
     L.lat_batch_run.argtypes = [vp, i, i, i, vp, vp]
     L.lat_batch_configure.argtypes = [vp, i, i, i, i]
+    L.lat_batch_autotune.argtypes = [vp, i, i, vp]
     L.lat_batch_get_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_set_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_destroy.argtypes = [vp]
     for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_set_links",
-                 "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_set_accept_log", "lat_save", "lat_load",
+                 "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_autotune", "lat_set_accept_log", "lat_save", "lat_load",
                  "lat_destroy", "lat_philox4x32_10", "lat_batch_create", "lat_batch_run",
-                 "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy", "lat_batch_configure"):
+                 "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy", "lat_batch_configure",
+                 "lat_batch_autotune"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -233,6 +236,13 @@ class Lattice:
                                       ctypes.byref(b)))
         return a.value, b.value
 
+    def autotune(self, n_hb=1, n_or=4) -> dict:
+        """Pick the fastest launch shape for this lattice; the lattice state is
+        restored afterwards."""
+        r = np.zeros(3, dtype=np.int32)
+        _check(lib.lat_autotune(self._h, int(n_hb), int(n_or), _ptr(r)))
+        return {"block_size": int(r[0]), "tile_order": int(r[1]), "max_waves_per_simd": int(r[2])}
+
     def set_accept_log(self, on=True):
         _check(lib.lat_set_accept_log(self._h, int(bool(on))))
 
@@ -303,6 +313,11 @@ class Batch:
     def configure(self, mode=0, block_size=256, sites_per_thread=1, grid=0):
         """mode 0: one launch per pass over all members; 1: persistent work list."""
         _check(lib.lat_batch_configure(self._h, int(mode), int(block_size), int(sites_per_thread), int(grid)))
+
+    def autotune(self, n_hb=1, n_or=4) -> dict:
+        r = np.zeros(2, dtype=np.int32)
+        _check(lib.lat_batch_autotune(self._h, int(n_hb), int(n_or), _ptr(r)))
+        return {"block_size": int(r[0]), "sites_per_thread": int(r[1])}
 
     def get_links(self, i) -> np.ndarray:
         d = self.descs[i]

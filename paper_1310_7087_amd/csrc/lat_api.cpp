@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -700,6 +701,143 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
     return LAT_OK;
 }
 
+}  // extern "C"
+
+// ===========================================================================
+// autotuner: launch shape of the sweep kernels, chosen by timing candidates
+// on the lattice itself; its state is saved before and restored after, so
+// the Markov chain is unchanged by tuning.
+// ===========================================================================
+namespace {
+
+std::string tune_key(const char* what, const std::vector<int>& v, int storage) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string name = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        name = prop.gcnArchName;
+    for (auto& ch : name)
+        if (ch == ' ' || ch == ':') ch = '_';
+    std::string k = std::string(what) + "_s" + std::to_string(storage);
+    for (int x : v) k += "_" + std::to_string(x);
+    return k + "_" + name;
+}
+
+bool tune_cache_get(const std::string& key, std::vector<int>& val) {
+    const char* path = std::getenv("LAT_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[400];
+        int a = 0, b = 0, c = 0, n = std::sscanf(line, "%399s %d %d %d", k, &a, &b, &c);
+        if (n == 4 && key == k) {
+            val = {a, b, c};
+            found = true;  // the last entry for a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_put(const std::string& key, const std::vector<int>& val) {
+    const char* path = std::getenv("LAT_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d\n", key.c_str(), val[0], val[1], val[2]);
+    std::fclose(f);
+}
+
+// Time one compound sweep (average of `reps`) with the handle's current shape.
+int time_compound(lat_ctx* h, int n_hb, int n_or, int reps, double* ms) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = enqueue_sweep(h, n_hb, n_or);  // warm-up
+    if (!rc) {
+        hipEventRecord(e0, h->stream);
+        for (int r = 0; r < reps && !rc; ++r) rc = enqueue_sweep(h, n_hb, n_or);
+        hipEventRecord(e1, h->stream);
+    }
+    hipError_t e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
+    *ms = t / reps;
+    return LAT_OK;
+}
+
+}  // namespace
+
+extern "C" int lat_autotune(lat_t h, int n_hb, int n_or, int result[3]) {
+    if (!h) return fail(LAT_EINVAL, "NULL handle");
+    if (n_hb < 0 || n_or < 0 || n_hb + n_or == 0) return fail(LAT_EINVAL, "bad sweep counts");
+    if (h->log_on) return fail(LAT_ESTATE, "switch the accept log off before tuning");
+    if (h->tshape[0]) return fail(LAT_ESTATE, "a 4-D work-group tile was requested explicitly");
+    const std::string key = tune_key("pass", {h->group, h->dims[0], h->dims[1], h->dims[2], h->dims[3]},
+                                     h->storage);
+    std::vector<int> best;
+    if (!tune_cache_get(key, best)) {
+        // save the whole device state (links, generator states, counters)
+        char* backup = nullptr;
+        HIP_TRY(hipMalloc(&backup, h->lay.total));
+        HIP_TRY(hipMemcpyAsync(backup, h->base, h->lay.total, hipMemcpyDeviceToDevice, h->stream));
+        const uint64_t hb0 = h->hb_sweeps, sw0 = h->sweeps;
+        const int keep_block = h->block, keep_order = h->tile_order, keep_lds = h->lds_reserve;
+        double best_ms = 1e30;
+        int rc = LAT_OK;
+        const int blocks[3] = {64, 128, 256};
+        const int caps[4] = {-1, 1, 2, 3};
+        for (int bi = 0; bi < 3 && !rc; ++bi)
+            for (int order = 0; order < 2 && !rc; ++order)
+                for (int ci = 0; ci < 4 && !rc; ++ci) {
+                    const int lds = caps[ci] > 0 ? occupancy_lds(caps[ci], blocks[bi]) : 0;
+                    if (caps[ci] > 0 && lds == 0) continue;
+                    h->block = blocks[bi];
+                    h->tile_order = order;
+                    h->lds_reserve = lds;
+                    double ms = 0.0;
+                    rc = time_compound(h, n_hb, n_or, 2, &ms);
+                    if (!rc && ms < best_ms) {
+                        best_ms = ms;
+                        best = {blocks[bi], order, caps[ci]};
+                    }
+                }
+        hipError_t e = hipMemcpyAsync(h->base, backup, h->lay.total, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        hipFree(backup);
+        h->hb_sweeps = hb0;
+        h->sweeps = sw0;
+        if (rc || e != hipSuccess || best.empty()) {
+            h->block = keep_block;
+            h->tile_order = keep_order;
+            h->lds_reserve = keep_lds;
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(LAT_EDEVICE, "autotune restore: %s", hipGetErrorString(e));
+            return fail(LAT_EDEVICE, "autotune found no runnable shape");
+        }
+        tune_cache_put(key, best);
+    }
+    h->block = best[0];
+    h->tile_order = best[1];
+    h->lds_reserve = best[2] > 0 ? occupancy_lds(best[2], best[0]) : 0;
+    drop_graphs(h);
+    if (result) {
+        result[0] = best[0];
+        result[1] = best[1];
+        result[2] = best[2];
+    }
+    return LAT_OK;
+}
+
+extern "C" {
+
 int lat_get_info(lat_t h, uint64_t* seed_used, uint64_t* hb_sweeps_done, uint64_t* sweeps_done) {
     if (!h) return fail(LAT_EINVAL, "NULL handle");
     if (seed_used) *seed_used = h->seed;
@@ -1108,6 +1246,95 @@ extern "C" int lat_batch_configure(lat_batch_t b, int mode, int block_size, int 
     b->tuned = true;
     batch_drop_graphs(b);
     return batch_build_table(b);
+}
+
+extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[2]) {
+    if (!b) return fail(LAT_EINVAL, "NULL batch");
+    if (n_hb < 0 || n_or < 0 || n_hb + n_or == 0) return fail(LAT_EINVAL, "bad sweep counts");
+    std::vector<int> key_v;
+    for (lat_t h : b->members) {
+        key_v.push_back(h->group);
+        for (int m = 0; m < 4; ++m) key_v.push_back(h->dims[m]);
+    }
+    // a compact key: member count plus a hash of the member shapes
+    uint64_t hsh = 1469598103934665603ull;
+    for (int x : key_v) hsh = (hsh ^ (uint64_t)(uint32_t)x) * 1099511628211ull;
+    const std::string key = tune_key("batch", {(int)b->members.size(), (int)(hsh & 0x7fffffff)}, b->storage);
+    std::vector<int> best;
+    if (!tune_cache_get(key, best)) {
+        std::vector<char*> backup(b->members.size(), nullptr);
+        int rc = LAT_OK;
+        for (size_t i = 0; i < b->members.size() && !rc; ++i) {
+            lat_ctx* h = b->members[i];
+            if (hipMalloc(&backup[i], h->lay.total) != hipSuccess) {
+                rc = fail(LAT_ENOMEM, "autotune backup");
+                break;
+            }
+            if (hipMemcpyAsync(backup[i], h->base, h->lay.total, hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+                rc = fail(LAT_EDEVICE, "autotune backup copy");
+        }
+        std::vector<std::pair<uint64_t, uint64_t>> counters;
+        for (lat_t h : b->members) counters.emplace_back(h->hb_sweeps, h->sweeps);
+        const int keep_block = b->block, keep_spt = b->spt;
+        double best_ms = 1e30;
+        const int blocks[3] = {64, 128, 256};
+        const int spts[3] = {1, 2, 4};
+        for (int bi = 0; bi < 3 && !rc; ++bi)
+            for (int si = 0; si < 3 && !rc; ++si) {
+                b->block = blocks[bi];
+                b->spt = spts[si];
+                rc = batch_build_table(b);
+                if (rc) break;
+                hipEvent_t e0, e1;
+                hipEventCreate(&e0);
+                hipEventCreate(&e1);
+                rc = batch_enqueue(b, 1, n_hb, n_or);  // warm-up and graph capture
+                if (!rc) {
+                    hipEventRecord(e0, b->stream);
+                    rc = batch_enqueue(b, 2, n_hb, n_or);
+                    hipEventRecord(e1, b->stream);
+                }
+                float t = 0.f;
+                if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
+                    t / 2 < best_ms) {
+                    best_ms = t / 2;
+                    best = {blocks[bi], spts[si], 0};
+                }
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+            }
+        hipStreamSynchronize(b->stream);
+        for (size_t i = 0; i < b->members.size(); ++i) {
+            if (!backup[i]) continue;
+            lat_ctx* h = b->members[i];
+            if (hipMemcpyAsync(h->base, backup[i], h->lay.total, hipMemcpyDeviceToDevice, b->stream) != hipSuccess && !rc)
+                rc = fail(LAT_EDEVICE, "autotune restore");
+        }
+        hipStreamSynchronize(b->stream);
+        for (char* p : backup)
+            if (p) hipFree(p);
+        for (size_t i = 0; i < b->members.size(); ++i) {
+            b->members[i]->hb_sweeps = counters[i].first;
+            b->members[i]->sweeps = counters[i].second;
+        }
+        if (rc || best.empty()) {
+            b->block = keep_block;
+            b->spt = keep_spt;
+            batch_build_table(b);
+            return rc ? rc : fail(LAT_EDEVICE, "batch autotune found no runnable shape");
+        }
+        tune_cache_put(key, best);
+    }
+    b->block = best[0];
+    b->spt = best[1];
+    b->tuned = true;
+    int rc = batch_build_table(b);
+    if (rc) return rc;
+    if (result) {
+        result[0] = best[0];
+        result[1] = best[1];
+    }
+    return LAT_OK;
 }
 
 extern "C" int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly) {

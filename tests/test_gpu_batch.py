@@ -91,3 +91,21 @@ def test_persistent_form_is_refused():
     with pytest.raises(P.LatError) as e:
         b.configure(1, 256, 1, 0)
     assert e.value.code == P.EUNSUPPORTED
+
+
+def test_batch_autotune_keeps_members():
+    descs = small_batch()
+    a = P.Batch(descs, storage=P.F32)
+    b = P.Batch(descs, storage=P.F32)
+    a.run(1, 1, 1)
+    b.run(1, 1, 1)
+    before = [a.get_links(i) for i in range(len(descs))]
+    shape = a.autotune(1, 4)
+    assert shape["block_size"] in (64, 128, 256) and shape["sites_per_thread"] in (1, 2, 4)
+    for i in range(len(descs)):
+        assert np.array_equal(a.get_links(i), before[i])
+    pa, _ = a.run(2, 1, 4)
+    pb, _ = b.run(2, 1, 4)
+    assert np.array_equal(pa, pb)
+    for i in range(len(descs)):
+        assert np.array_equal(a.get_links(i), b.get_links(i))

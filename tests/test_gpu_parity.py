@@ -364,3 +364,24 @@ def test_full_size_32x8_flux4_one_compound_sweep():
     pg, lg = g.measure()
     po, lo = o.measure()
     assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
+
+
+def test_autotune_keeps_the_chain(tmp_path, monkeypatch):
+    monkeypatch.setenv("LAT_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    for storage in (P.F64, P.F32_C12):
+        a = P.Lattice(3, (16, 16, 16, 4), 5.9, seed=3, storage=storage)
+        b = P.Lattice(3, (16, 16, 16, 4), 5.9, seed=3, storage=storage)
+        a.sweep(1, 1)
+        b.sweep(1, 1)
+        before = a.get_links()
+        info0 = a.info()
+        shape = a.autotune(1, 4)
+        assert shape["block_size"] in (64, 128, 256) and shape["tile_order"] in (0, 1)
+        assert np.array_equal(a.get_links(), before) and a.info() == info0
+        a.sweep(1, 4)
+        b.sweep(1, 4)
+        assert np.array_equal(a.get_links(), b.get_links())
+        # a second tuner call is answered from the cache file
+        c = P.Lattice(3, (16, 16, 16, 4), 5.9, seed=3, storage=storage)
+        assert c.autotune(1, 4) == shape
+    assert (tmp_path / "tune.txt").read_text().count("\n") == 2
