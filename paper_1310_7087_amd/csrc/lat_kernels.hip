@@ -79,11 +79,14 @@ constexpr int SUB_B[3] = {1, 2, 2};
 // SU(3) pass
 // ---------------------------------------------------------------------------
 // Update of the link U_mu(x) at half-lattice index s of the pass parity.
-template <class ST, int KIND, bool REUNIT, int RNG>
+// MU >= 0 fixes the direction at compile time (the staple then is one
+// straight-line block the scheduler can interleave); MU = -1 reads it from
+// the arguments.
+template <class ST, int KIND, bool REUNIT, int RNG, int MU = -1>
 LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     using T = typename ST::real;
     using M = m3<T>;
-    const int p = a.parity, q = 1 - p, mu = a.mu;
+    const int p = a.parity, q = 1 - p, mu = MU >= 0 ? MU : a.mu;
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
     const coord4 c = decode(a.g, s, p);
@@ -183,10 +186,10 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     }
 }
 
-template <class ST, int KIND, bool REUNIT, int RNG>
+template <class ST, int KIND, bool REUNIT, int RNG, int MU>
 __global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
     const int64_t s = thread_site(a);
-    if (s >= 0) su3_site<ST, KIND, REUNIT, RNG>(a, s);
+    if (s >= 0) su3_site<ST, KIND, REUNIT, RNG, MU>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,10 +801,21 @@ LAT_HOST_DEV_INLINE unsigned pass_blocks(const PassArgs& a, int block) {
     return (unsigned)((a.g.vh + block - 1) / block);
 }
 
+// Overrelaxation is specialised per direction; the heat bath takes the
+// direction at run time (its straight-line form exceeds the register file).
 template <class ST, int KIND, bool RE, int RNG>
 hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
     const unsigned nb = pass_blocks(a, block);
-    hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG>), dim3(nb), dim3(block), a.lds_reserve, st, a);
+    if constexpr (KIND == 1) {
+        switch (a.mu) {
+            case 0: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 0>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
+            case 1: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 1>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
+            case 2: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 2>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
+            default: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 3>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
+        }
+    } else {
+        hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, -1>), dim3(nb), dim3(block), a.lds_reserve, st, a);
+    }
     return hipGetLastError();
 }
 template <class ST, int KIND, bool RE, int RNG>
