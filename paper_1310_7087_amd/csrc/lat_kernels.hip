@@ -113,10 +113,6 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     }
     constexpr bool PREPARE = (KIND == 0 && RNG != LAT_RNG_MRG_I);
     kp_first first[3];
-    if constexpr (PREPARE) {
-#pragma unroll
-        for (int g = 0; g < 3; ++g) first[g] = kp_prepare(d, g);
-    }
 
     // staple A = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
     //                           + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)]
@@ -135,6 +131,14 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
         const M b0 = load_link<ST>(L, vp, q, mu, s_mn);
         const M b1 = load_link<ST>(L, vp, p, nu, s_pmmn);
         const M b2 = load_link<ST>(L, vp, q, nu, s_mn);
+        if constexpr (PREPARE) {
+            // while the first direction's links are in flight, turn the
+            // random numbers of each subgroup's first try into its candidate
+            if (nu == (mu == 0 ? 1 : 0)) {
+#pragma unroll
+                for (int g = 0; g < 3; ++g) first[g] = kp_prepare(d, g);
+            }
+        }
         mac_na(A, mul_na(f0, f1), f2);
         mac_an(A, mul_nn(b0, b1), b2);
     }
