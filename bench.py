@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -72,6 +73,14 @@ def binned(x, nbins=10):
     return float(b.mean()), float(b.std(ddof=1) / np.sqrt(nbins))
 
 
+def observables(plaq, poly):
+    """Mean and binned error of P, P_s, P_t, Re L and |L| over a series."""
+    import numpy as np
+    series = {"P": plaq[:, 0], "P_s": plaq[:, 1], "P_t": plaq[:, 2], "ReL": poly[:, 0],
+              "absL": np.hypot(poly[:, 0], poly[:, 1])}
+    return {k: dict(zip(("mean", "err"), binned(v))) for k, v in series.items()}
+
+
 def storage_of(P, form):
     return {"f64": P.F64, "f32": P.F32, "f32c12": P.F32_C12}[form]
 
@@ -80,9 +89,12 @@ def run_form(P, form: str, steps: int, warmup: int):
     import torch
     V = volume(DIMS)
     lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=3, start=P.COLD)
-    shape = lat.autotune(N_HB, N_OR)
-    log(f"[{form}] launch shape {shape}; warmup {warmup} steps")
+    log(f"[{form}] warmup {warmup} steps")
     lat.run(warmup, N_HB, N_OR, measure_every=1)
+    # launch shape tuned on the warmed-up links (the state is restored)
+    shape = lat.autotune(N_HB, N_OR)
+    log(f"[{form}] launch shape {shape}")
+    lat.run(1, N_HB, N_OR, measure_every=1)  # graph capture of the tuned shape
     torch.cuda.synchronize()
     log(f"[{form}] timing {steps} steps")
     t0 = time.perf_counter()
@@ -94,13 +106,12 @@ def run_form(P, form: str, steps: int, warmup: int):
     t_hb, t_or = lat.profile_passes(N_HB, N_OR, reps=5)
     b = BYTES_PER_LINK[form]
     pass_bytes = 4.5 * V * b  # reads all 4V links, writes the V/2 updated ones
-    p_mean, p_err = binned(plaq[:, 0])
+    obs = observables(plaq, poly)
     res = {
         "link_updates_per_s": updates / dt,
         "ms_per_step": 1e3 * dt / steps,
         "launch_shape": shape,
-        "plaquette_mean": p_mean,
-        "plaquette_err": p_err,
+        "observables": obs,
         "plaquette_last": [float(x) for x in plaq[-1]],
         "polyakov_last": [float(poly[-1][0]), float(poly[-1][1])],
         "hb_pass_us": 1e3 * t_hb,
@@ -123,7 +134,9 @@ def run_large(P, sweeps: int = 40):
     out = {}
     for form in ("f64", "f32c12"):
         lat = P.Lattice(3, dims, 6.0, 0, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=23, start=P.HOT)
+        lat.run(5, N_HB, N_OR, measure_every=0)
         shape = lat.autotune(N_HB, N_OR)
+        lat.run(1, N_HB, N_OR, measure_every=1)  # graph capture
         t0 = time.perf_counter()
         plaq, _ = lat.run(sweeps, N_HB, N_OR, measure_every=1)
         dt = time.perf_counter() - t0
@@ -142,26 +155,30 @@ def run_large(P, sweeps: int = 40):
     out["speedup_f32c12_vs_f64"] = out["f32c12"]["link_updates_per_s"] / out["f64"]["link_updates_per_s"]
     out["delta_plaquette_f32c12_minus_f64"] = (out["f32c12"]["plaquette_mean_last_half"]
                                               - out["f64"]["plaquette_mean_last_half"])
-    out["config"] = {"lattice": list(dims), "beta": 6.0, "start": "hot", "seed": 23, "sweeps": sweeps,
-                     "n_hb": N_HB, "n_or": N_OR}
+    out["config"] = {"lattice": list(dims), "beta": 6.0, "start": "hot", "seed": 23,
+                     "sweeps_before_timing": 6, "sweeps": sweeps, "n_hb": N_HB, "n_or": N_OR}
     return out
 
 
-def run_batch(P, sweeps: int = 10):
+def run_batch(P, sweeps: int = 10, precision_sweeps: int = 1000):
     """64 independent lattices (SU(2)/SU(3), 8^3x4 .. 24^3x6, coupling scan):
-    the FP32 batch launch against the same lattices run one by one in FP64."""
+    the FP32 batch launch against the same lattices run one by one in FP64
+    (the plain form) and against the FP64 batch."""
     from inputs import batch_workloads
     ws = batch_workloads(64, seed=11)
     descs = [dict(group=w.group, dims=w.dims, beta=w.beta, flux=w.flux, seed=w.seed, start=w.start,
                   lattice_id=w.lattice_id) for w in ws]
     links = sum(4 * volume(w.dims) for w in ws)
-    bt = P.Batch(descs, storage=P.F32)
-    shape = bt.autotune(N_HB, N_OR)
-    bt.run(2, N_HB, N_OR, measure=False)
-    t0 = time.perf_counter()
-    bt.run(sweeps, N_HB, N_OR, measure=False)
-    dt_b = time.perf_counter() - t0
-    bt.close()
+    rates, shapes = {}, {}
+    for name, storage in (("f32_batched", P.F32), ("f64_batched", P.F64)):
+        bt = P.Batch(descs, storage=storage)
+        bt.run(20, N_HB, N_OR, measure=False)
+        shapes[name] = bt.autotune(N_HB, N_OR)
+        bt.run(sweeps, N_HB, N_OR, measure=False)  # captures the graph timed below
+        t0 = time.perf_counter()
+        bt.run(sweeps, N_HB, N_OR, measure=False)
+        rates[name] = sweeps * 5 * links / (time.perf_counter() - t0)
+        bt.close()
     singles = [P.Lattice(d["group"], d["dims"], d["beta"], 0, storage=P.F64, rng=P.RNG_PHILOX,
                          seed=d["seed"], lattice_id=d["lattice_id"], start=d["start"]) for d in descs]
     for s in singles:
@@ -169,15 +186,50 @@ def run_batch(P, sweeps: int = 10):
     t0 = time.perf_counter()
     for s in singles:
         s.run(sweeps, N_HB, N_OR, measure_every=0)
-    dt_s = time.perf_counter() - t0
+    rates["f64_one_by_one"] = sweeps * 5 * links / (time.perf_counter() - t0)
     for s in singles:
         s.close()
-    r_b = sweeps * 5 * links / dt_b
-    r_s = sweeps * 5 * links / dt_s
-    log(f"[batch] F32 batched {r_b:.3e} vs F64 one by one {r_s:.3e} link updates/s")
-    return {"lattices": len(ws), "total_links": links, "sweeps": sweeps, "launch_shape": shape,
-            "f32_batched_link_updates_per_s": r_b, "f64_one_by_one_link_updates_per_s": r_s,
-            "speedup": r_b / r_s}
+    log(f"[batch] F32 batched {rates['f32_batched']:.3e}, F64 batched {rates['f64_batched']:.3e}, "
+        f"F64 one by one {rates['f64_one_by_one']:.3e} link updates/s")
+    out = {"lattices": len(ws), "total_links": links, "sweeps": sweeps, "launch_shapes": shapes,
+           "f32_batched_link_updates_per_s": rates["f32_batched"],
+           "f64_batched_link_updates_per_s": rates["f64_batched"],
+           "f64_one_by_one_link_updates_per_s": rates["f64_one_by_one"],
+           "speedup": rates["f32_batched"] / rates["f64_one_by_one"]}
+    if precision_sweeps > 0:
+        out["precision"] = batch_precision(P, descs, precision_sweeps)
+    return out
+
+
+def batch_precision(P, descs, n, therm=100):
+    """<P> of every member, FP32 batch against FP64 batch: the same Haar
+    starts and random numbers, `n` compound sweeps, the first `therm`
+    discarded.  The chains decorrelate, so the members' differences are
+    combined as a weighted mean with its error."""
+    import numpy as np
+    series = {}
+    for name, storage in (("f32", P.F32), ("f64", P.F64)):
+        bt = P.Batch(descs, storage=storage)
+        bt.autotune(N_HB, N_OR)
+        ps = np.empty((n, len(descs)))
+        for k in range(n):
+            p, _ = bt.run(1, N_HB, N_OR, measure=True)
+            ps[k] = p[:, 0]
+        bt.close()
+        series[name] = ps
+    delta, err = [], []
+    for i in range(len(descs)):
+        (mb, eb), (ms, es) = binned(series["f32"][therm:, i]), binned(series["f64"][therm:, i])
+        delta.append(mb - ms)
+        err.append(math.hypot(eb, es))
+    delta, err = np.array(delta), np.array(err)
+    w = 1.0 / err ** 2
+    dw = float(np.sum(w * delta) / np.sum(w))
+    ew = float(np.sqrt(1.0 / np.sum(w)))
+    log(f"[batch] weighted <P> difference FP32 - FP64 {dw:.2e} +- {ew:.1e}")
+    return {"sweeps": n, "thermalisation": therm, "weighted_mean_delta_P": dw, "weighted_mean_delta_P_err": ew,
+            "chi2_per_member": float(np.mean((delta / err) ** 2)),
+            "max_abs_member_delta_P": float(np.max(np.abs(delta)))}
 
 
 def cpu_baseline(steps: int):
@@ -224,6 +276,8 @@ def main() -> int:
                     help="storage forms to time; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the 64^3x16 and batch measurements")
+    ap.add_argument("--precision-sweeps", type=int, default=1000,
+                    help="compound sweeps of the batch precision comparison (0 skips it)")
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="steps of the CPU oracle in the bounded baseline sample (about 1 s each on 16 cores)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -288,14 +342,19 @@ def main() -> int:
         "forms": {f: {k: v for k, v in results[f].items() if k != "pass_bytes"} for f in forms},
     }
     if "f64" in results:
+        ref = results["f64"]["observables"]
         for f in forms:
             if f != "f64":
                 fr = out["forms"][f]
                 fr["speedup_vs_f64"] = results[f]["link_updates_per_s"] / results["f64"]["link_updates_per_s"]
-                fr["delta_plaquette_vs_f64"] = results[f]["plaquette_mean"] - results["f64"]["plaquette_mean"]
+                # difference of each observable's long-run mean from the FP64 one
+                # (the chains decorrelate, so it is a statistical comparison)
+                fr["delta_vs_f64"] = {
+                    k: {"delta": v["mean"] - ref[k]["mean"], "err": math.hypot(v["err"], ref[k]["err"])}
+                    for k, v in results[f]["observables"].items()}
     if not args.no_extras:
         out["su3_64x16"] = run_large(P)
-        out["batch_64_lattices"] = run_batch(P)
+        out["batch_64_lattices"] = run_batch(P, precision_sweeps=args.precision_sweeps)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)

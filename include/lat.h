@@ -161,10 +161,12 @@ int lat_set_links(lat_t h, const double* host, size_t n_doubles);
 int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words);
 /*
  * Kernel profiling (the paper's run-time kernel profiling, Sec. 3.2): runs
- * `reps` compound sweeps (n_hb, n_or) with every pass launched on its own
- * between HIP events on the handle's stream, and returns the average
+ * `reps` compound sweeps (n_hb, n_or) with the passes launched directly on
+ * the handle's stream, HIP events before the heat-bath passes, between the
+ * two kinds and after the overrelaxation passes, and returns the average
  * duration in milliseconds of a heat-bath pass (ms_hb) and of an
- * overrelaxation pass (ms_or).  The lattice advances as with lat_sweep.
+ * overrelaxation pass (ms_or), each the span of its back-to-back passes
+ * divided by their number.  The lattice advances as with lat_sweep.
  * Synchronises.  Either output may be NULL.
  */
 int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, double* ms_or);

@@ -659,15 +659,17 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
     if (n_hb < 0 || n_or < 0 || reps < 1 || n_hb + n_or == 0) return fail(LAT_EINVAL, "bad profile arguments");
     if (h->log_on) return fail(LAT_ESTATE, "switch the accept log off before profiling");
     const int total = n_hb + n_or;
-    const int npass = 8 * total;
-    std::vector<hipEvent_t> ev((size_t)npass * reps + 1);
+    // three events per repetition: before the heat-bath passes, between the
+    // two kinds, after the overrelaxation passes; the passes of one kind run
+    // back to back between them
+    std::vector<hipEvent_t> ev((size_t)3 * reps);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     PassArgs a = pass_args(h);
-    int k = 0;
-    HIP_TRY(hipEventRecord(ev[k++], h->stream));
     for (int r = 0; r < reps; ++r) {
+        HIP_TRY(hipEventRecord(ev[3 * r], h->stream));
         for (int s = 0; s < total; ++s) {
             const int kind = s < n_hb ? 0 : 1;
+            if (s == n_hb) HIP_TRY(hipEventRecord(ev[3 * r + 1], h->stream));
             a.hb_offset = kind == 0 ? s : 0;
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p) {
@@ -675,26 +677,23 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
                     a.parity = p;
                     HIP_TRY(lat_launch_pass(h->group, h->storage, kind, s == total - 1, h->rng, a, h->block,
                                             h->stream));
-                    HIP_TRY(hipEventRecord(ev[k++], h->stream));
                 }
         }
+        if (n_or == 0) HIP_TRY(hipEventRecord(ev[3 * r + 1], h->stream));
+        HIP_TRY(hipEventRecord(ev[3 * r + 2], h->stream));
         if (n_hb > 0) HIP_TRY(lat_launch_bump(h->hb(), n_hb, h->stream));
         h->hb_sweeps += (uint64_t)n_hb;
         h->sweeps += 1;
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
     double sum_hb = 0.0, sum_or = 0.0;
-    k = 0;
-    for (int r = 0; r < reps; ++r)
-        for (int s = 0; s < total; ++s)
-            for (int j = 0; j < 8; ++j) {
-                float ms = 0.f;
-                // the event after the previous pass starts this pass's interval; the
-                // first pass of a repetition after a counter bump starts at the bump
-                HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
-                ++k;
-                (s < n_hb ? sum_hb : sum_or) += ms;
-            }
+    for (int r = 0; r < reps; ++r) {
+        float t1 = 0.f, t2 = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t1, ev[3 * r], ev[3 * r + 1]));
+        HIP_TRY(hipEventElapsedTime(&t2, ev[3 * r + 1], ev[3 * r + 2]));
+        sum_hb += t1;
+        sum_or += t2;
+    }
     for (auto& e : ev) hipEventDestroy(e);
     if (ms_hb) *ms_hb = n_hb ? sum_hb / (8.0 * n_hb * reps) : 0.0;
     if (ms_or) *ms_or = n_or ? sum_or / (8.0 * n_or * reps) : 0.0;
@@ -752,24 +751,38 @@ void tune_cache_put(const std::string& key, const std::vector<int>& val) {
 }
 
 // Time one compound sweep (average of `reps`) with the handle's current shape.
-int time_compound(lat_ctx* h, int n_hb, int n_or, int reps, double* ms) {
+// Time `reps` compound sweeps of the current launch shape.  Every trial
+// starts from the saved device state `backup`, so that all candidate shapes
+// are timed on the same links (the heat bath's cost depends on them); the
+// first trial also captures the shape's graph.  The faster of two trials.
+int time_compound(lat_ctx* h, const char* backup, int n_hb, int n_or, int reps, double* ms) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    int rc = enqueue_sweep(h, n_hb, n_or);  // warm-up
-    if (!rc) {
+    int rc = LAT_OK;
+    double best = 1e30;
+    for (int trial = 0; trial < 3 && !rc; ++trial) {
+        if (hipMemcpyAsync(h->base, backup, h->lay.total, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
+            rc = fail(LAT_EDEVICE, "autotune restore");
+            break;
+        }
+        if (trial == 0) {  // graph capture and warm-up
+            rc = enqueue_sweep(h, n_hb, n_or);
+            continue;
+        }
         hipEventRecord(e0, h->stream);
         for (int r = 0; r < reps && !rc; ++r) rc = enqueue_sweep(h, n_hb, n_or);
         hipEventRecord(e1, h->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (!rc && e != hipSuccess) rc = fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
+        if (!rc && t / reps < best) best = t / reps;
     }
-    hipError_t e = hipEventSynchronize(e1);
-    float t = 0.f;
-    if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
-    if (e != hipSuccess) return fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
-    *ms = t / reps;
+    *ms = best;
     return LAT_OK;
 }
 
@@ -803,7 +816,7 @@ extern "C" int lat_autotune(lat_t h, int n_hb, int n_or, int result[3]) {
                     h->tile_order = order;
                     h->lds_reserve = lds;
                     double ms = 0.0;
-                    rc = time_compound(h, n_hb, n_or, 2, &ms);
+                    rc = time_compound(h, backup, n_hb, n_or, 2, &ms);
                     if (!rc && ms < best_ms) {
                         best_ms = ms;
                         best = {blocks[bi], order, caps[ci]};
@@ -1288,17 +1301,27 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
                 hipEvent_t e0, e1;
                 hipEventCreate(&e0);
                 hipEventCreate(&e1);
-                rc = batch_enqueue(b, 1, n_hb, n_or);  // warm-up and graph capture
-                if (!rc) {
+                // every trial starts from the saved members (the heat bath's
+                // cost depends on the links); the first also captures the graph
+                for (int trial = 0; trial < 3 && !rc; ++trial) {
+                    for (size_t i = 0; i < b->members.size() && !rc; ++i)
+                        if (hipMemcpyAsync(b->members[i]->base, backup[i], b->members[i]->lay.total,
+                                           hipMemcpyDeviceToDevice, b->stream) != hipSuccess)
+                            rc = fail(LAT_EDEVICE, "autotune restore");
+                    if (rc) break;
+                    if (trial == 0) {
+                        rc = batch_enqueue(b, 1, n_hb, n_or);
+                        continue;
+                    }
                     hipEventRecord(e0, b->stream);
                     rc = batch_enqueue(b, 2, n_hb, n_or);
                     hipEventRecord(e1, b->stream);
-                }
-                float t = 0.f;
-                if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
-                    t / 2 < best_ms) {
-                    best_ms = t / 2;
-                    best = {blocks[bi], spts[si], 0};
+                    float t = 0.f;
+                    if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
+                        t / 2 < best_ms) {
+                        best_ms = t / 2;
+                        best = {blocks[bi], spts[si], 0};
+                    }
                 }
                 hipEventDestroy(e0);
                 hipEventDestroy(e1);
