@@ -16,7 +16,7 @@ import pytest
 
 import oracle as O
 from helpers import det_error, to_matrices, unitarity_error
-from inputs import SU2_4x4, SU3_16x4, su3_32x8
+from inputs import SU2_4x4, SU3_16x4, SU3_64x16, su3_32x8
 
 pytestmark = pytest.mark.gpu
 
@@ -385,3 +385,56 @@ def test_autotune_keeps_the_chain(tmp_path, monkeypatch):
         c = P.Lattice(3, (16, 16, 16, 4), 5.9, seed=3, storage=storage)
         assert c.autotune(1, 4) == shape
     assert (tmp_path / "tune.txt").read_text().count("\n") == 2
+
+
+def test_full_size_64x16_heat_bath_sweep(tmp_path, monkeypatch):
+    """SU(3) 64^3x16, beta 6.0, Haar start (seed 23), FP64, in the launch
+    shape the autotuner picks: every link and the observables after one
+    heat-bath sweep against the oracle."""
+    monkeypatch.setenv("LAT_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = SU3_64x16
+    O.set_threads(O.get_threads())
+    g, o = pair(w.group, w.dims, w.beta, seed=w.seed, start=O.HOT)
+    g.autotune(1, 4)
+    g.sweep(1, 0)
+    o.sweep(1, 0)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
+
+
+def test_full_size_64x16_twelve_real_heat_bath_sweep(tmp_path, monkeypatch):
+    """The same lattice in FP32 12-real storage, in its tuned launch shape,
+    from links three compound sweeps off the Haar start: one heat-bath sweep
+    against the oracle started from the identical (FP32-rounded) links.
+    Decisions are taken in FP64 on both sides; a flipped one is expected about
+    once per 10^7 and moves only the links it reaches within the sweep."""
+    monkeypatch.setenv("LAT_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    w = SU3_64x16
+    O.set_threads(O.get_threads())
+    src = P.Lattice(w.group, w.dims, w.beta, storage=P.F64, seed=w.seed, start=P.HOT)
+    src.run(3, 1, 4, measure_every=0)
+    links = src.get_links()
+    src.close()
+    g = P.Lattice(w.group, w.dims, w.beta, storage=P.F32_C12, seed=w.seed, start=P.COLD)
+    g.set_links(links)
+    del links
+    g.autotune(1, 4)
+    o = O.Lattice(w.group, w.dims, w.beta, seed=w.seed, start=O.COLD)
+    o.set_links(g.get_links())
+    g.set_accept_log(True)
+    o.enable_accept_log(True)
+    g.sweep(1, 0)
+    o.sweep(1, 0)
+    la, lb = g.accept_log(), o.accept_log()
+    flips = int((la != lb).sum())
+    assert flips <= 1e-6 * la.size
+    d = np.abs(g.get_links() - o.get_links()).max(axis=(1, 2))
+    if flips == 0:
+        assert d.max() < TOL32
+    else:
+        assert (d > TOL32).sum() <= 500 * flips
+    pg, _ = g.measure()
+    po, _ = o.measure()
+    assert maxdiff(pg, po) < 1e-6
