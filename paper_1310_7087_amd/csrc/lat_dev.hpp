@@ -281,8 +281,11 @@ struct u4 {
 LAT_DEV u4 philox10(u4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32->64 multiply per word gives both halves (a single
+        // v_mad_u64_u32 instead of separate low and high multiplies)
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x, m1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)m0, hi0 = (uint32_t)(m0 >> 32);
+        const uint32_t lo1 = (uint32_t)m1, hi1 = (uint32_t)(m1 >> 32);
         c = {hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -356,7 +359,7 @@ LAT_DEV int kp(double alpha, int nhit, DR& d, int g, qt<double>& x) {
     for (int t = 0; t < nhit; ++t) {
         double R[4];
         d.try4(g, t, R);
-        const double c = cos(TWO_PI * R[1]);
+        const double c = cospi(2.0 * R[1]);  // cos(2 pi R2), exact argument
         const double lam2 = -(log(R[0]) + c * c * log(R[2])) / (2.0 * alpha);
         if (R[3] * R[3] <= 1.0 - lam2) {
             double D[2];
@@ -365,7 +368,7 @@ LAT_DEV int kp(double alpha, int nhit, DR& d, int g, qt<double>& x) {
             const double ct = 2.0 * D[0] - 1.0;
             const double st = sqrt(1.0 - ct * ct);
             double sp, cp;
-            sincos(TWO_PI * D[1], &sp, &cp);
+            sincospi(2.0 * D[1], &sp, &cp);  // phi = 2 pi R6
             x = {1.0 - 2.0 * lam2, s * st * cp, s * st * sp, s * ct};
             return t;
         }
@@ -389,14 +392,14 @@ LAT_DEV kp_first kp_prepare(DR& d, int g) {
     kp_first f;
     double R[4], D[2];
     d.try4(g, 0, R);
-    const double c = cos(TWO_PI * R[1]);
+    const double c = cospi(2.0 * R[1]);  // cos(2 pi R2), exact argument
     f.num = log(R[0]) + c * c * log(R[2]);
     f.r4sq = R[3] * R[3];
     d.dir2(g, D);
     const double ct = 2.0 * D[0] - 1.0;
     const double st = sqrt(1.0 - ct * ct);
     double sp, cp;
-    sincos(TWO_PI * D[1], &sp, &cp);
+    sincospi(2.0 * D[1], &sp, &cp);  // phi = 2 pi R6
     f.dx = st * cp;
     f.dy = st * sp;
     f.dz = ct;
@@ -411,7 +414,7 @@ LAT_DEV int kp_prepared(double alpha, int nhit, DR& d, int g, const kp_first& f,
         for (t = 1; t < nhit; ++t) {
             double R[4];
             d.try4(g, t, R);
-            const double c = cos(TWO_PI * R[1]);
+            const double c = cospi(2.0 * R[1]);  // cos(2 pi R2), exact argument
             lam2 = -(log(R[0]) + c * c * log(R[2])) / (2.0 * alpha);
             if (R[3] * R[3] <= 1.0 - lam2) break;
         }
