@@ -38,6 +38,7 @@ DIMS = (32, 32, 32, 8)
 BETA = 5.9
 FLUX = 1
 N_HB, N_OR = 1, 4
+REPEATS = 5
 BYTES_PER_LINK = {"f64": 144, "f32": 72, "f32c12": 48}
 KERNEL_SOURCES = ["paper_1310_7087_amd/csrc/lat_kernels.hip", "paper_1310_7087_amd/csrc/lat_dev.hpp",
                   "paper_1310_7087_amd/csrc/lat_types.hpp"]
@@ -90,17 +91,25 @@ def run_form(P, form: str, steps: int, warmup: int):
     V = volume(DIMS)
     lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=3, start=P.COLD)
     log(f"[{form}] warmup {warmup} steps")
-    lat.run(warmup, N_HB, N_OR, measure_every=1)
+    early, _ = lat.run(warmup, N_HB, N_OR, measure_every=1)
     # launch shape tuned on the warmed-up links (the state is restored)
     shape = lat.autotune(N_HB, N_OR)
     log(f"[{form}] launch shape {shape}")
     lat.run(1, N_HB, N_OR, measure_every=1)  # graph capture of the tuned shape
     torch.cuda.synchronize()
-    log(f"[{form}] timing {steps} steps")
-    t0 = time.perf_counter()
-    plaq, poly = lat.run(steps, N_HB, N_OR, measure_every=1)  # queued on the device, synchronises
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    log(f"[{form}] timing {steps} steps in {REPEATS} repeats")
+    series, times = [], []
+    for k in range(REPEATS):
+        n = steps // REPEATS + (1 if k < steps % REPEATS else 0)
+        t0 = time.perf_counter()
+        series.append(lat.run(n, N_HB, N_OR, measure_every=1))  # queued on the device, synchronises
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0, n))
+    import numpy as np
+    plaq = np.concatenate([x[0] for x in series])
+    poly = np.concatenate([x[1] for x in series])
+    dt = sum(t for t, _ in times)
+    per_repeat = sorted(n * (N_HB + N_OR) * 4 * volume(DIMS) / t for t, n in times)
     updates = steps * (N_HB + N_OR) * 4 * V
     # event-timed passes of the same kernels on the same stream
     t_hb, t_or = lat.profile_passes(N_HB, N_OR, reps=5)
@@ -109,8 +118,11 @@ def run_form(P, form: str, steps: int, warmup: int):
     obs = observables(plaq, poly)
     res = {
         "link_updates_per_s": updates / dt,
+        "median_of_repeats": per_repeat[len(per_repeat) // 2],
+        "repeat_range": [per_repeat[0], per_repeat[-1]],
         "ms_per_step": 1e3 * dt / steps,
         "launch_shape": shape,
+        "early_plaquettes": [float(x) for x in early[:10, 0]],
         "observables": obs,
         "plaquette_last": [float(x) for x in plaq[-1]],
         "polyakov_last": [float(poly[-1][0]), float(poly[-1][1])],
@@ -232,6 +244,34 @@ def batch_precision(P, descs, n, therm=100):
             "max_abs_member_delta_P": float(np.max(np.abs(delta)))}
 
 
+def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
+    """Read + write GB/s of a plain device-to-device copy of `mib` MiB (the
+    practical HBM ceiling beside the 8 TB/s peak), timed with events."""
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(steps: int):
     import oracle as O
     cores = len(os.sched_getaffinity(0))
@@ -243,11 +283,21 @@ def cpu_baseline(steps: int):
         ref.sweep(N_HB, N_OR)
         ref.measure()
     dt = time.perf_counter() - t0
+    # one thread on an eighth of the volume (about the same time per update)
+    O.set_threads(1)
+    small = (16, 16, 16, 8)
+    ref1 = O.Lattice(3, small, BETA, flux=FLUX, rng=O.RNG_PHILOX, seed=3, start=O.COLD)
+    t0 = time.perf_counter()
+    ref1.sweep(N_HB, N_OR)
+    dt1 = time.perf_counter() - t0
+    O.set_threads(cores)
     return {"value": steps * (N_HB + N_OR) * 4 * V / dt, "unit": "link updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} step(s) (1 HB + 4 OR compound sweep + plaquette/Polyakov) of the same "
                       f"SU(3) 32^3x8 lattice from the cold start, FP64, {cores} OpenMP threads",
-            "seconds": dt}
+            "seconds": dt, "cpu_model": cpu_model(),
+            "single_thread_value": (N_HB + N_OR) * 4 * volume(small) / dt1,
+            "single_thread_sample": "one (1 HB + 4 OR) compound sweep of SU(3) 16^3x8 from the cold start, 1 thread"}
 
 
 def traffic_for(kernel: str, form: str):
@@ -302,6 +352,7 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"calibration copy of {args.copy_mib} MiB done")
         del src, dst
+    copy_gbs = copy_bandwidth(torch)
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     results = {}
@@ -338,6 +389,7 @@ def main() -> int:
                    "lattice": list(DIMS), "beta": BETA, "flux_quanta": FLUX, "n_hb": N_HB, "n_or": N_OR,
                    "storage": head, "parallelism": "single_gpu"},
         "hbm_fraction_algorithmic": r["hbm_fraction"],
+        "copy_GBs": copy_gbs,
         "roofline": roofline,
         "forms": {f: {k: v for k, v in results[f].items() if k != "pass_bytes"} for f in forms},
     }
@@ -349,6 +401,10 @@ def main() -> int:
                 fr["speedup_vs_f64"] = results[f]["link_updates_per_s"] / results["f64"]["link_updates_per_s"]
                 # difference of each observable's long-run mean from the FP64 one
                 # (the chains decorrelate, so it is a statistical comparison)
+                # the same start and random numbers: the first sweeps track the
+                # FP64 trajectory until the chains decorrelate
+                fr["early_abs_delta_P_vs_f64"] = [
+                    abs(a - b) for a, b in zip(results[f]["early_plaquettes"], results["f64"]["early_plaquettes"])]
                 fr["delta_vs_f64"] = {
                     k: {"delta": v["mean"] - ref[k]["mean"], "err": math.hypot(v["err"], ref[k]["err"])}
                     for k, v in results[f]["observables"].items()}

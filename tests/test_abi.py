@@ -90,3 +90,20 @@ def test_load_rejects_missing_and_corrupt_files(tmp_path):
     bad = tmp_path / "bad.ckpt"
     bad.write_bytes(b"NOTACKPT" + b"\0" * 200)
     assert P.lib.lat_load(ctypes.byref(h), str(bad).encode(), None) == P.ECORRUPT
+
+
+def test_maximum_sizes():
+    """Per-thread link addresses are 32-bit byte offsets within one plane of
+    the half lattice: the largest accepted lattice keeps a plane below 4 GiB
+    (SU(3) FP64 128^4 = 154 GB of links, within one GPU's 288 GB); one step
+    beyond is rejected before any device call."""
+    import paper_1310_7087_amd as P
+    V = 128 ** 4
+    n = P.device_bytes(3, (128, 128, 128, 128))
+    assert 4 * V * 144 <= n < 4 * V * 144 + (1 << 30)
+    assert P.device_bytes(3, (256, 128, 128, 128)) == 0
+    assert P.device_bytes(3, (256, 128, 128, 128), storage=P.F32_C12) == 0
+    assert P.device_bytes(3, (256, 128, 128, 128), storage=P.F32) > 0
+    with pytest.raises(P.LatError) as e:
+        P.Lattice(3, (256, 128, 128, 128), 6.0)
+    assert e.value.code == P.EINVAL and "32-bit" in P.lib.lat_last_error().decode()
