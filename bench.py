@@ -10,8 +10,8 @@ steps * (1 + 4) * 4 V / time, with the lattice resident in HBM; the plain
 FP64 18-real form gives the headline value.  Each form first picks its
 launch shape with the library's autotuner (the lattice state is restored).
 
-Also reported: the FP32 and 12-real FP32 storage forms (speed-up over FP64
-and the difference of their mean plaquette from the FP64 one), the roofline
+Also reported: the FP32, 12-real FP32 and 12-real FP64 storage forms
+(speed-up over FP64 and the difference of their observables from FP64), the roofline
 of the dominant pass kernel (event-timed in this run), SU(3) 64^3 x 16 (the
 case that does not fit the last-level cache), the 64-lattice batch in FP32
 against the same lattices run one by one in FP64, and the FP64 CPU oracle
@@ -39,7 +39,7 @@ BETA = 5.9
 FLUX = 1
 N_HB, N_OR = 1, 4
 REPEATS = 5
-BYTES_PER_LINK = {"f64": 144, "f32": 72, "f32c12": 48}
+BYTES_PER_LINK = {"f64": 144, "f32": 72, "f32c12": 48, "f64c12": 96}
 KERNEL_SOURCES = ["paper_1310_7087_amd/csrc/lat_kernels.hip", "paper_1310_7087_amd/csrc/lat_dev.hpp",
                   "paper_1310_7087_amd/csrc/lat_types.hpp"]
 
@@ -83,7 +83,7 @@ def observables(plaq, poly):
 
 
 def storage_of(P, form):
-    return {"f64": P.F64, "f32": P.F32, "f32c12": P.F32_C12}[form]
+    return {"f64": P.F64, "f32": P.F32, "f32c12": P.F32_C12, "f64c12": P.F64_C12}[form]
 
 
 def run_form(P, form: str, steps: int, warmup: int):
@@ -322,7 +322,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--forms", default="f64,f32,f32c12",
+    ap.add_argument("--forms", default="f64,f32,f32c12,f64c12",
                     help="storage forms to time; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the 64^3x16 and batch measurements")

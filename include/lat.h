@@ -57,6 +57,9 @@ extern "C" {
                           reunitarisation, heat-bath acceptance and observable sums */
 #define LAT_F32_C12 2  /* as LAT_F32, SU(3) only: first two rows stored (12 reals),
                           row 3 = conj(row1 x row2) rebuilt on every load */
+#define LAT_F64_C12 3  /* FP64 arithmetic, SU(3) only: first two rows stored
+                          (12 doubles), row 3 = conj(row1 x row2) rebuilt in FP64
+                          on every load; two thirds of LAT_F64's link bytes */
 
 /* ---- random number generators (one parameter picks it, Sec. 3.4) ---- */
 #define LAT_RNG_MRG32K3A 0  /* per-site MRG32k3a streams, 2^127 apart */
@@ -70,7 +73,7 @@ typedef struct lat_ctx* lat_t;
 typedef struct lat_batch* lat_batch_t;
 
 typedef struct {
-    int storage;         /* LAT_F64 (default), LAT_F32, LAT_F32_C12 */
+    int storage;         /* LAT_F64 (default), LAT_F32, LAT_F32_C12, LAT_F64_C12 */
     int rng;             /* LAT_RNG_PHILOX (default), LAT_RNG_MRG32K3A, LAT_RNG_CONST */
     double rng_const;    /* value of every uniform for LAT_RNG_CONST, in (0,1) */
     int start;           /* LAT_HOT (default) or LAT_COLD */
@@ -235,7 +238,8 @@ typedef struct {
 /* n lattices described by d[0..n-1]; common supplies storage, nhit, stream
  * and block_size (0 = tuned by lat_batch_autotune or the default); the
  * generator must be Philox (each member keyed by its own seed and
- * lattice_id); with LAT_F32_C12 the SU(2) members use LAT_F32; the
+ * lattice_id); with LAT_F32_C12 (LAT_F64_C12) the SU(2) members use
+ * LAT_F32 (LAT_F64); the
  * per-lattice fields of common are ignored.  Each member's
  * results are bit-identical to the same lattice run alone. */
 int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common);

@@ -17,11 +17,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblat.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EIO, ECORRUPT, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-F64, F32, F32_C12 = 0, 1, 2
+F64, F32, F32_C12, F64_C12 = 0, 1, 2, 3
 RNG_MRG32K3A, RNG_PHILOX, RNG_CONST = 0, 1, 2
 COLD, HOT = 0, 1
 
-STORAGE_NAMES = {F64: "f64", F32: "f32", F32_C12: "f32c12"}
+STORAGE_NAMES = {F64: "f64", F32: "f32", F32_C12: "f32c12", F64_C12: "f64c12"}
 
 
 class LatError(RuntimeError):

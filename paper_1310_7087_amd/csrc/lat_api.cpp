@@ -96,7 +96,7 @@ std::vector<uint32_t> mrg_site_states(uint64_t seed, int64_t nsites) {
 int ncomp(int group) { return group == 3 ? 18 : 4; }
 size_t bytes_per_link(int group, int storage) {
     if (group == 2) return storage == LAT_F64 ? 32 : 16;
-    return storage == LAT_F64 ? 144 : storage == LAT_F32 ? 72 : 48;
+    return storage == LAT_F64 ? 144 : storage == LAT_F32 ? 72 : storage == LAT_F64_C12 ? 96 : 48;
 }
 
 struct Layout {
@@ -117,8 +117,9 @@ int make_layout(int group, const int d[4], int storage, int rng, int layout, Lay
     for (int m = 0; m < 4; ++m)
         if (d[m] < 2 || (d[m] & 1)) return fail(LAT_EINVAL, "extent %d = %d must be even and >= 2", m, d[m]);
     if (group != 2 && group != 3) return fail(LAT_EINVAL, "group must be 2 or 3, got %d", group);
-    if (storage < LAT_F64 || storage > LAT_F32_C12) return fail(LAT_EINVAL, "unknown storage %d", storage);
-    if (group == 2 && storage == LAT_F32_C12) return fail(LAT_EUNSUPPORTED, "12-real storage is SU(3) only");
+    if (storage < LAT_F64 || storage > LAT_F64_C12) return fail(LAT_EINVAL, "unknown storage %d", storage);
+    if (group == 2 && (storage == LAT_F32_C12 || storage == LAT_F64_C12))
+        return fail(LAT_EUNSUPPORTED, "12-real storage is SU(3) only");
     const int64_t V = (int64_t)d[0] * d[1] * d[2] * d[3];
     if (V / 2 > 0x7FFFFFFFLL) return fail(LAT_EINVAL, "lattice too large");
     LatGeom g;
@@ -506,7 +507,7 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     h->block = o.block_size ? o.block_size : 256;
     h->tile_order = o.tile_order;
     int cap = o.max_waves_per_simd;
-    if (cap == 0) cap = (group == 3 && o.storage == LAT_F64) ? 1 : -1;
+    if (cap == 0) cap = (group == 3 && (o.storage == LAT_F64 || o.storage == LAT_F64_C12)) ? 1 : -1;
     h->lds_reserve = cap > 0 ? -cap : 0;  // resolved once the work-group size is known
     if (o.tile[0]) {
         for (int k = 0; k < 4; ++k) h->tshape[k] = o.tile[k];
@@ -1215,6 +1216,7 @@ extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, cons
         mo.lattice_id = d[i].lattice_id;
         // 12-real compression applies to SU(3) members; SU(2) members keep FP32 quaternions
         if (d[i].group == 2 && mo.storage == LAT_F32_C12) mo.storage = LAT_F32;
+        if (d[i].group == 2 && mo.storage == LAT_F64_C12) mo.storage = LAT_F64;
         lat_t h = nullptr;
         int rc = lat_create(&h, d[i].group, d[i].Nx, d[i].Ny, d[i].Nz, d[i].Nt, d[i].beta, d[i].field_flux, &mo);
         if (rc) {

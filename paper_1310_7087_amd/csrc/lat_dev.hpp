@@ -561,6 +561,30 @@ struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
         st_plane(base, pb, 2, off, make_float4(m.e[1][1].re, m.e[1][1].im, m.e[1][2].re, m.e[1][2].im));
     }
 };
+struct st_f64c12 {  // SU(3), rows 1-2 as 6 planes of (re, im) doubles; row 3 rebuilt
+    using real = double;
+    using mat = m3<double>;
+    static constexpr int NP = 6;
+    static constexpr int VB = 16;
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        mat m;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double2 v = ld_plane<double2>(base, pb, k, off);
+            m.e[k / 3][k % 3] = {v.x, v.y};
+        }
+        third_row(m);
+        return m;
+    }
+    LAT_DEV static void store(char* base, int64_t plane_stride, int64_t s, const mat& m) {
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) st_plane(base, pb, k, off, make_double2(m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im));
+    }
+};
 struct sq_f64 {  // SU(2), 4 doubles: 2 planes of double2
     using real = double;
     using mat = qt<double>;

@@ -861,6 +861,7 @@ hipError_t lat_launch_pass(int group, int storage, int kind, bool reunit, int rn
         switch (storage) {
             case LAT_ST_F64: return pass_dispatch<st_f64, true>(kind, reunit, rng, a, block, st);
             case LAT_ST_F32: return pass_dispatch<st_f32, true>(kind, reunit, rng, a, block, st);
+            case LAT_ST_F64C12: return pass_dispatch<st_f64c12, true>(kind, reunit, rng, a, block, st);
             default: return pass_dispatch<st_f32c12, true>(kind, reunit, rng, a, block, st);
         }
     }
@@ -893,6 +894,7 @@ hipError_t lat_launch_init(int group, int storage, int rng, const InitArgs& a, h
         switch (storage) {
             case LAT_ST_F64: return init_dispatch<st_f64, true>(rng, a, st);
             case LAT_ST_F32: return init_dispatch<st_f32, true>(rng, a, st);
+            case LAT_ST_F64C12: return init_dispatch<st_f64c12, true>(rng, a, st);
             default: return init_dispatch<st_f32c12, true>(rng, a, st);
         }
     }
@@ -921,6 +923,7 @@ hipError_t lat_launch_measure(int group, int storage, const MeasArgs& a, double*
         switch (storage) {
             case LAT_ST_F64: return meas_dispatch<st_f64, true>(a, out, slot_counter, st);
             case LAT_ST_F32: return meas_dispatch<st_f32, true>(a, out, slot_counter, st);
+            case LAT_ST_F64C12: return meas_dispatch<st_f64c12, true>(a, out, slot_counter, st);
             default: return meas_dispatch<st_f32c12, true>(a, out, slot_counter, st);
         }
     }
@@ -942,6 +945,7 @@ hipError_t lat_launch_convert(int group, int storage, bool to_dev, const LatGeom
         switch (storage) {
             case LAT_ST_F64: return conv_dispatch<st_f64, 3>(to_dev, g, canon, links, st);
             case LAT_ST_F32: return conv_dispatch<st_f32, 3>(to_dev, g, canon, links, st);
+            case LAT_ST_F64C12: return conv_dispatch<st_f64c12, 3>(to_dev, g, canon, links, st);
             default: return conv_dispatch<st_f32c12, 3>(to_dev, g, canon, links, st);
         }
     }
@@ -978,6 +982,7 @@ hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t*
     switch (storage) {
         case LAT_ST_F64: batch_launch_typed<st_f64, sq_f64>(b, mode, grid, block, st); break;
         case LAT_ST_F32: batch_launch_typed<st_f32, sq_f32>(b, mode, grid, block, st); break;
+        case LAT_ST_F64C12: batch_launch_typed<st_f64c12, sq_f64>(b, mode, grid, block, st); break;
         default: batch_launch_typed<st_f32c12, sq_f32>(b, mode, grid, block, st); break;
     }
     if (b.n_hb > 0) hipLaunchKernelGGL(batch_bump, dim3(nb), dim3(256), 0, st, b, counters, b.n_hb * b.n_sweeps);

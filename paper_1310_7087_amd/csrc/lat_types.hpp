@@ -9,6 +9,7 @@
 #define LAT_ST_F64 0
 #define LAT_ST_F32 1
 #define LAT_ST_F32C12 2
+#define LAT_ST_F64C12 3
 
 struct LatGeom {
     int nx, ny, nz, nt;

@@ -42,7 +42,7 @@ def test_device_bytes_layout():
     import paper_1310_7087_amd as P
     # 32^3 x 8 SU(3): links are 4 V * (144 | 72 | 48) bytes plus small scratch
     V = 32 ** 3 * 8
-    for st, b in ((P.F64, 144), (P.F32, 72), (P.F32_C12, 48)):
+    for st, b in ((P.F64, 144), (P.F32, 72), (P.F32_C12, 48), (P.F64_C12, 96)):
         n = P.device_bytes(3, (32, 32, 32, 8), storage=st)
         assert 4 * V * b <= n < 4 * V * b + (1 << 20)
     # MRG state adds 24 bytes per site
@@ -65,6 +65,8 @@ def test_device_bytes_layout():
     (3, (4, 4, 4, 4), 5.7, {"rng": 2, "rng_const": 1.0}, -1),
     (3, (4, 4, 4, 4), 5.7, {"block_size": 100}, -1),
     (2, (4, 4, 4, 4), 2.3, {"storage": 2}, -7),
+    (2, (4, 4, 4, 4), 2.3, {"storage": 3}, -7),
+    (3, (4, 4, 4, 4), 5.7, {"storage": 4}, -1),
     (2, (4, 4, 4, 4), 2.3, {"rng": 0, "seed": 4294944443}, -1),
 ])
 def test_create_rejects_bad_arguments_without_a_device(group, dims, beta, kw, code):

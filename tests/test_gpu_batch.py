@@ -27,7 +27,7 @@ def small_batch():
             dict(group=3, dims=(12, 12, 12, 6), beta=6.0, seed=11, lattice_id=4)]
 
 
-@pytest.mark.parametrize("storage", [P.F32, P.F64, P.F32_C12])
+@pytest.mark.parametrize("storage", [P.F32, P.F64, P.F32_C12, P.F64_C12])
 @pytest.mark.parametrize("shape", [(0, 256, 1, 0), (0, 64, 1, 0), (0, 128, 3, 0)])
 def test_members_equal_single_runs(storage, shape):
     descs = small_batch()
@@ -35,7 +35,9 @@ def test_members_equal_single_runs(storage, shape):
     b.configure(*shape)
     pb, lb = b.run(3, 1, 4)
     for i, d in enumerate(descs):
-        st = P.F32 if (d["group"] == 2 and storage == P.F32_C12) else storage
+        st = storage
+        if d["group"] == 2 and storage in (P.F32_C12, P.F64_C12):  # SU(2) members keep all 4 reals
+            st = P.F32 if storage == P.F32_C12 else P.F64
         single = P.Lattice(d["group"], d["dims"], d["beta"], d.get("flux", 0), storage=st,
                            rng=P.RNG_PHILOX, seed=d["seed"], lattice_id=d["lattice_id"], start=P.HOT)
         for _ in range(3):

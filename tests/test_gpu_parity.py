@@ -442,3 +442,26 @@ def test_full_size_64x16_twelve_real_heat_bath_sweep(tmp_path, monkeypatch):
     pg, _ = g.measure()
     po, _ = o.measure()
     assert maxdiff(pg, po) < 1e-6
+
+
+def test_f64_twelve_real_form():
+    """FP64 12-real storage (row 3 rebuilt in FP64 on every load) against the
+    FP64 oracle at the FP64 bar: links round-trip, one heat-bath sweep from the
+    Haar start, and the measured workload's first compound sweep from cold."""
+    o = O.Lattice(3, (16, 16, 16, 4), 5.69, seed=7, start=O.HOT)
+    links = o.get_links()
+    g = P.Lattice(3, (16, 16, 16, 4), 5.69, seed=7, start=P.HOT, storage=P.F64_C12)
+    assert maxdiff(g.get_links(), links) < 1e-14  # same Haar start, row 3 rebuilt
+    g.set_links(links)
+    assert maxdiff(g.get_links(), links) < 1e-14
+    g.sweep(1, 0)
+    o.sweep(1, 0)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    w = su3_32x8(1)
+    g, o = pair(w.group, w.dims, w.beta, flux=w.flux, seed=w.seed, start=O.COLD, storage=P.F64_C12)
+    g.sweep(1, 4)
+    o.sweep(1, 4)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
