@@ -185,6 +185,7 @@ struct lat_ctx {
     bool own_mem = false;
     int block = 256;
     int tile_order = 0;
+    int alternate = 1;    // odd-parity passes walk the z-slab order backwards
     int tshape[4] = {0, 0, 0, 0};
     int lds_reserve = 0;  // caps the waves per SIMD of the pass kernels
     uint64_t hb_sweeps = 0, sweeps = 0;
@@ -241,6 +242,7 @@ PassArgs pass_args(const lat_ctx* h) {
     a.nyb = 1;
     a.zslab = 1;
     a.lds_reserve = h->lds_reserve;
+    a.reverse = 0;
     if (a.tile_order == 0) {
         // z-slabs per XCD need whole work-groups per z-plane and 8 | Nz
         const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
@@ -266,6 +268,7 @@ int enqueue_sweep(lat_ctx* h, int n_hb, int n_or) {
             for (int p = 0; p < 2; ++p) {
                 a.mu = mu;
                 a.parity = p;
+                a.reverse = h->alternate ? p : 0;
                 HIP_TRY(lat_launch_pass(h->group, h->storage, kind, reunit, h->rng, a, h->block, h->stream));
             }
     }
@@ -676,6 +679,7 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
                 for (int p = 0; p < 2; ++p) {
                     a.mu = mu;
                     a.parity = p;
+                    a.reverse = h->alternate ? p : 0;  // as in the captured sweep
                     HIP_TRY(lat_launch_pass(h->group, h->storage, kind, s == total - 1, h->rng, a, h->block,
                                             h->stream));
                 }

@@ -24,13 +24,16 @@ namespace {
 // the slab faces (the host falls back to order 1 when 8 does not divide Nz
 // or work-groups do not tile whole z-planes); 1: identity; 2: reversed;
 // 3: one contiguous range of tiles per XCD.
-LAT_DEV int64_t tile_index(int order, int nyb = 1, int zslab = 1, int nz = 1) {
+LAT_DEV int64_t tile_index(int order, int nyb = 1, int zslab = 1, int nz = 1, int reverse = 0) {
     const int64_t nb = gridDim.x, b = blockIdx.x;
     if (order == 1) return b;
     if (order == 2) return nb - 1 - b;
     if (order == 0) {
         const int k = (int)(b & 7);
         int64_t j = b >> 3;
+        // walking the slab backwards on every other pass starts a pass on the
+        // links the previous pass touched last, still in this XCD's L2
+        if (reverse) j = (nb >> 3) - 1 - j;
         const int yb = (int)(j % nyb);
         j /= nyb;
         const int zl = (int)(j % zslab);
@@ -47,7 +50,7 @@ LAT_DEV int64_t tile_index(int order, int nyb = 1, int zslab = 1, int nz = 1) {
 // (x/2, y, z, t) per work-group so that neighbour links are shared inside
 // the work-group and its XCD.
 LAT_DEV int64_t thread_site(const PassArgs& a) {
-    const int64_t tile = tile_index(a.tile_order, a.nyb, a.zslab, a.g.nz);
+    const int64_t tile = tile_index(a.tile_order, a.nyb, a.zslab, a.g.nz, a.reverse);
     if (a.tshape[0] == 0) {
         const int64_t s = tile * (int64_t)blockDim.x + threadIdx.x;
         return s < a.g.vh ? s : -1;

@@ -38,6 +38,7 @@ struct PassArgs {
     int tcount[4];         // tiles per direction
     int nyb, zslab;        // z-slab order: work-groups per z-plane, z-planes per XCD
     int lds_reserve;       // dynamic LDS bytes reserved per work-group (caps occupancy)
+    int reverse;           // z-slab order walked backwards (every other pass)
 };
 
 // Initialisation of one lattice.
