@@ -138,6 +138,31 @@ def run_form(P, form: str, steps: int, warmup: int):
     return res
 
 
+def precision_study(P, steps: int, therm: int = 200):
+    """Long runs of every storage form on the headline lattice from the same
+    cold start and random numbers; the difference of each observable's mean
+    from the FP64 one, with binned errors (the chains decorrelate after a few
+    sweeps, so this bounds the precision forms' systematic error)."""
+    import numpy as np
+    out = {"steps": steps, "thermalisation": therm}
+    obs = {}
+    for form in ("f64", "f32", "f32c12", "f64c12"):
+        lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=3, start=P.COLD)
+        lat.run(therm, N_HB, N_OR, measure_every=0)
+        lat.autotune(N_HB, N_OR)
+        plaq, poly = lat.run(steps, N_HB, N_OR, measure_every=1)
+        lat.close()
+        series = {"P": plaq[:, 0], "P_s": plaq[:, 1], "P_t": plaq[:, 2], "ReL": poly[:, 0],
+                  "absL": np.hypot(poly[:, 0], poly[:, 1])}
+        obs[form] = {k: binned(v, 50) for k, v in series.items()}
+        log(f"[precision] {form}: <P> = {obs[form]['P'][0]:.7f} +- {obs[form]['P'][1]:.1e}")
+    out["means"] = {f: {k: {"mean": m, "err": e} for k, (m, e) in o.items()} for f, o in obs.items()}
+    out["delta_vs_f64"] = {f: {k: {"delta": obs[f][k][0] - obs["f64"][k][0],
+                                   "err": math.hypot(obs[f][k][1], obs["f64"][k][1])} for k in obs[f]}
+                           for f in obs if f != "f64"}
+    return out
+
+
 def run_large(P, sweeps: int = 40):
     """SU(3) 64^3 x 16, beta 6.0, Haar start (seed 23): FP64 18-real against
     FP32 12-real on the lattice that does not fit the 256 MB last-level cache."""
@@ -328,6 +353,9 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the 64^3x16 and batch measurements")
     ap.add_argument("--precision-sweeps", type=int, default=1000,
                     help="compound sweeps of the batch precision comparison (0 skips it)")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="only run the long FP32/12-real vs FP64 comparison of every observable "
+                         "(STEPS measured steps per form) and print its JSON line")
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="steps of the CPU oracle in the bounded baseline sample (about 1 s each on 16 cores)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -343,6 +371,11 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     import paper_1310_7087_amd as P
+
+    if args.precision_study > 0:
+        print(json.dumps({"precision_study": precision_study(P, args.precision_study),
+                          "workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or"}), flush=True)
+        return 0
 
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
