@@ -465,3 +465,20 @@ def test_f64_twelve_real_form():
     pg, lg = g.measure()
     po, lo = o.measure()
     assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
+
+
+@pytest.mark.parametrize("storage", [P.F64, P.F32_C12])
+def test_graph_replays_equal_eager_launches(storage):
+    """Every replay of the captured compound-sweep graph against the same
+    passes launched one by one (the profiling path), with eager measurements
+    and link reads between the replays."""
+    a = P.Lattice(3, (8, 8, 8, 4), 5.8, 1, storage=storage, seed=12)
+    b = P.Lattice(3, (8, 8, 8, 4), 5.8, 1, storage=storage, seed=12)
+    for _ in range(4):
+        a.sweep(1, 4)                      # graph replay
+        b.profile_passes(1, 4, reps=1)     # the same passes, launched eagerly
+        assert np.array_equal(a.get_links(), b.get_links())
+        pa, la = a.measure()
+        pb, lb = b.measure()
+        assert np.array_equal(pa, pb) and np.array_equal(la, lb)
+    assert a.info() == b.info()
