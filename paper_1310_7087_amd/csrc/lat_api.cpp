@@ -158,7 +158,7 @@ int make_layout(int group, const int d[4], int storage, int rng, int layout, Lay
     off += 256;
     L.nb_plaq = (int)((g.vh + 255) / 256);
     const int64_t vs = (int64_t)d[0] * d[1] * d[2];
-    L.nb_poly = (int)((vs + 255) / 256);
+    L.nb_poly = (int)((vs + 63) / 64);  // 64 spatial sites per Polyakov work-group
     L.partial_off = off;
     L.partial_bytes = (size_t)(4 * L.nb_plaq + 2 * L.nb_poly) * sizeof(double);
     off = align_up(off + L.partial_bytes, 256);
@@ -185,6 +185,7 @@ struct lat_ctx {
     bool own_mem = false;
     int block = 256;
     int tile_order = 0;
+    int meas_lds = 0;     // occupancy cap of the plaquette kernel (dynamic LDS bytes)
     int alternate = 1;    // odd-parity passes walk the z-slab order backwards
     int tshape[4] = {0, 0, 0, 0};
     int lds_reserve = 0;  // caps the waves per SIMD of the pass kernels
@@ -339,6 +340,14 @@ int enqueue_measure(lat_ctx* h, bool series) {
     m.partial = h->partial();
     m.nb_plaq = h->lay.nb_plaq;
     m.nb_poly = h->lay.nb_poly;
+    m.nyb = 0;
+    m.zslab = 0;
+    const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
+    if (plane % 256 == 0 && h->lay.g.nz % 8 == 0) {
+        m.nyb = (int)(plane / 256);
+        m.zslab = h->lay.g.nz / 8;
+    }
+    m.lds_reserve = h->meas_lds;
     HIP_TRY(lat_launch_measure(h->group, h->storage, m, h->meas(), series ? h->slot() : nullptr, h->stream));
     return LAT_OK;
 }
@@ -536,6 +545,9 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     }
     h->seed = seed;
     if (h->lds_reserve < 0) h->lds_reserve = occupancy_lds(-h->lds_reserve, h->block);
+    // FP64 plaquettes run best at one wave per SIMD (less L2 thrashing), the
+    // FP32 forms at full occupancy
+    if (group == 3 && (o.storage == LAT_F64 || o.storage == LAT_F64_C12)) h->meas_lds = occupancy_lds(1, 256);
     rc = init_handle(h, &o);
     if (rc) {
         std::string keep = g_err;

@@ -434,11 +434,25 @@ LAT_DEV void block_reduce_store(double (&v)[NV], double* out, int64_t stride, in
 // tile run on the same XCD (blocks b and b+8) right after each other, so the
 // links one parity reads as neighbours are still in L2 for the other.  The
 // grid is padded to whole groups of 16; padding blocks contribute nothing.
-LAT_DEV void plaq_block(int nb, int& tile, int& parity) {
+LAT_DEV void plaq_block(const MeasArgs& a, int& tile, int& parity) {
     const int b = blockIdx.x;
+    if (a.zslab) {
+        // XCD k (work-group b runs on XCD b mod 8) takes z-slab k, both
+        // parities of a region in turn, as the pass kernels do
+        const int k = b & 7;
+        int j = b >> 3;
+        parity = j & 1;
+        j >>= 1;
+        const int yb = j % a.nyb;
+        j /= a.nyb;
+        const int zl = j % a.zslab;
+        const int t = j / a.zslab;
+        tile = yb + a.nyb * ((k * a.zslab + zl) + a.g.nz * t);
+        return;
+    }
     tile = ((b >> 4) << 3) | (b & 7);
     parity = (b >> 3) & 1;
-    if (tile >= nb) tile = -1;
+    if (tile >= a.nb_plaq) tile = -1;
 }
 
 template <class ST>
@@ -446,7 +460,7 @@ __global__ void __launch_bounds__(256) su3_plaq(MeasArgs a) {
     using T = typename ST::real;
     using M = m3<T>;
     int tile, p;
-    plaq_block(a.nb_plaq, tile, p);
+    plaq_block(a, tile, p);
     const int q = 1 - p;
     const int64_t s = tile < 0 ? a.g.vh : tile * (int64_t)blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
@@ -476,7 +490,7 @@ __global__ void __launch_bounds__(256) su2_plaq(MeasArgs a) {
     using T = typename ST::real;
     using Q = qt<T>;
     int tile, p;
-    plaq_block(a.nb_plaq, tile, p);
+    plaq_block(a, tile, p);
     const int q = 1 - p;
     const int64_t s = tile < 0 ? a.g.vh : tile * (int64_t)blockDim.x + threadIdx.x;
     double v[2] = {0.0, 0.0};
@@ -501,46 +515,56 @@ __global__ void __launch_bounds__(256) su2_plaq(MeasArgs a) {
     if (tile >= 0) block_reduce_store<2>(v, a.partial, 2 * (int64_t)a.nb_plaq, (int64_t)p * a.nb_plaq + tile);
 }
 
-template <class ST>
-__global__ void __launch_bounds__(256) su3_poly(MeasArgs a) {
-    using T = typename ST::real;
-    const int64_t xs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t vs = (int64_t)a.g.nx * a.g.ny * a.g.nz;
-    double v[2] = {0.0, 0.0};
-    if (xs < vs) {
-        const int x = (int)(xs % a.g.nx);
-        const int y = (int)((xs / a.g.nx) % a.g.ny);
-        const int z = (int)(xs / ((int64_t)a.g.nx * a.g.ny));
-        m3<T> P = identity3<T>();
-        for (int t = 0; t < a.g.nt; ++t) {
-            const coord4 c = {x, y, z, t};
-            const int par = (x + y + z + t) & 1;
-            P = mul_nn(P, load_link<ST>(a.links, a.g.vh_pad, par, 3, half_index(a.g, c)));
-        }
-        v[0] = ((double)P.e[0][0].re + (double)P.e[1][1].re + (double)P.e[2][2].re) * (1.0 / 3.0);
-        v[1] = ((double)P.e[0][0].im + (double)P.e[1][1].im + (double)P.e[2][2].im) * (1.0 / 3.0);
-    }
-    block_reduce_store<2>(v, a.partial + 4 * (int64_t)a.nb_plaq, a.nb_poly, blockIdx.x);
+// Polyakov loop: a work-group covers 64 spatial sites; wave c multiplies the
+// temporal links of t-chunk c (t in [c Nt/4, (c+1) Nt/4)) of each site, and
+// wave 0 multiplies the four partial products in order, so the dependent
+// chain of loads and products is a quarter of Nt long.
+template <class T>
+LAT_DEV void poly_mul(m3<T>& P, const m3<T>& U) { P = mul_nn(P, U); }
+template <class T>
+LAT_DEV void poly_mul(qt<T>& P, const qt<T>& U) { P = qmul(P, U); }
+template <class T>
+LAT_DEV void poly_set_one(m3<T>& P) { P = identity3<T>(); }
+template <class T>
+LAT_DEV void poly_set_one(qt<T>& P) { P = {T(1), T(0), T(0), T(0)}; }
+template <class T>
+LAT_DEV void poly_trace(const m3<T>& P, double v[2]) {
+    v[0] = ((double)P.e[0][0].re + (double)P.e[1][1].re + (double)P.e[2][2].re) * (1.0 / 3.0);
+    v[1] = ((double)P.e[0][0].im + (double)P.e[1][1].im + (double)P.e[2][2].im) * (1.0 / 3.0);
+}
+template <class T>
+LAT_DEV void poly_trace(const qt<T>& P, double v[2]) {
+    v[0] = (double)P.q0;  // (1/2) Tr of an SU(2) element is real
+    v[1] = 0.0;
 }
 
 template <class ST>
-__global__ void __launch_bounds__(256) su2_poly(MeasArgs a) {
-    using T = typename ST::real;
-    const int64_t xs = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) lat_poly(MeasArgs a) {
+    using Mat = typename ST::mat;
+    __shared__ Mat part[3][64];
+    const int c = threadIdx.x >> 6, i = threadIdx.x & 63;
+    const int64_t xs = blockIdx.x * (int64_t)64 + i;
     const int64_t vs = (int64_t)a.g.nx * a.g.ny * a.g.nz;
-    double v[2] = {0.0, 0.0};
+    Mat P;
+    poly_set_one(P);
+    int x = 0, y = 0, z = 0;
     if (xs < vs) {
-        const int x = (int)(xs % a.g.nx);
-        const int y = (int)((xs / a.g.nx) % a.g.ny);
-        const int z = (int)(xs / ((int64_t)a.g.nx * a.g.ny));
-        qt<T> P = {T(1), T(0), T(0), T(0)};
-        for (int t = 0; t < a.g.nt; ++t) {
-            const coord4 c = {x, y, z, t};
-            const int par = (x + y + z + t) & 1;
-            P = qmul(P, load_link<ST>(a.links, a.g.vh_pad, par, 3, half_index(a.g, c)));
+        x = (int)(xs % a.g.nx);
+        y = (int)((xs / a.g.nx) % a.g.ny);
+        z = (int)(xs / ((int64_t)a.g.nx * a.g.ny));
+        const int t0 = (c * a.g.nt) / 4, t1 = ((c + 1) * a.g.nt) / 4;
+        for (int t = t0; t < t1; ++t) {
+            const coord4 cc = {x, y, z, t};
+            poly_mul(P, load_link<ST>(a.links, a.g.vh_pad, (x + y + z + t) & 1, 3, half_index(a.g, cc)));
         }
-        v[0] = (double)P.q0;  // (1/2) Tr of an SU(2) element is real
-        v[1] = 0.0;
+    }
+    if (c > 0) part[c - 1][i] = P;
+    __syncthreads();
+    double v[2] = {0.0, 0.0};
+    if (c == 0 && xs < vs) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) poly_mul(P, part[k][i]);
+        poly_trace(P, v);
     }
     block_reduce_store<2>(v, a.partial + 4 * (int64_t)a.nb_plaq, a.nb_poly, blockIdx.x);
 }
@@ -907,15 +931,11 @@ hipError_t lat_launch_init(int group, int storage, int rng, const InitArgs& a, h
 
 template <class ST, bool SU3>
 static hipError_t meas_dispatch(const MeasArgs& a, double* out, uint32_t* slot, hipStream_t st) {
-    dim3 gp((unsigned)(16 * ((a.nb_plaq + 7) / 8)));
+    dim3 gp((unsigned)(a.zslab ? 2 * a.nb_plaq : 16 * ((a.nb_plaq + 7) / 8)));
     dim3 gl((unsigned)a.nb_poly);
-    if constexpr (SU3) {
-        hipLaunchKernelGGL((su3_plaq<ST>), gp, dim3(256), 0, st, a);
-        hipLaunchKernelGGL((su3_poly<ST>), gl, dim3(256), 0, st, a);
-    } else {
-        hipLaunchKernelGGL((su2_plaq<ST>), gp, dim3(256), 0, st, a);
-        hipLaunchKernelGGL((su2_poly<ST>), gl, dim3(256), 0, st, a);
-    }
+    if constexpr (SU3) hipLaunchKernelGGL((su3_plaq<ST>), gp, dim3(256), a.lds_reserve, st, a);
+    else hipLaunchKernelGGL((su2_plaq<ST>), gp, dim3(256), a.lds_reserve, st, a);
+    hipLaunchKernelGGL((lat_poly<ST>), gl, dim3(256), 0, st, a);
     hipLaunchKernelGGL(meas_final, dim3(1), dim3(256), 0, st, a, out, slot);
     return hipGetLastError();
 }

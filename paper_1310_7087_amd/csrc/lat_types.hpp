@@ -59,6 +59,8 @@ struct MeasArgs {
     double* partial;      // [4][nblocks]: P_s sums, P_t sums, Re L, Im L
     int nb_plaq;          // blocks of the plaquette kernel
     int nb_poly;          // blocks of the Polyakov kernel
+    int nyb, zslab;       // z-slab order of the plaquette blocks (zslab 0: interleaved)
+    int lds_reserve;      // dynamic LDS per plaquette work-group (caps occupancy)
 };
 
 // One member of a batch of independent lattices.
