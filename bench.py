@@ -11,11 +11,13 @@ FP64 18-real form gives the headline value.  Each form first picks its
 launch shape with the library's autotuner (the lattice state is restored).
 
 Also reported: the FP32, 12-real FP32 and 12-real FP64 storage forms
-(speed-up over FP64 and the difference of their observables from FP64), the roofline
-of the dominant pass kernel (event-timed in this run), SU(3) 64^3 x 16 (the
-case that does not fit the last-level cache), the 64-lattice batch in FP32
-against the same lattices run one by one in FP64, and the FP64 CPU oracle
-timed on a bounded sample of the headline workload on the host cores.
+(speed-up over FP64 and the difference of their observables from FP64), the
+roofline of the dominant pass kernel (event-timed in this run), SU(3)
+64^3 x 16 (the case that does not fit the last-level cache), the 64-lattice
+batch in FP32 against the same lattices run one by one in FP64, the paper's
+own Table 1 working sweeps (SU(3) 32^4, SU(2) 44^4; its 2011 figures as
+context), and the FP64 CPU oracle timed on a bounded sample of the headline
+workload on the host cores.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -297,6 +299,39 @@ def cpu_model() -> str:
     return "unknown"
 
 
+# The paper's Table 1 working sweeps (one heat-bath sweep with NHIT = 10 and
+# reunitarisation, plus the measurement; Haar start), with the link-update
+# rates derived from its seconds per sweep on its own 2011 GPUs: context only.
+PAPER_TABLE1 = [
+    {"group": 3, "dims": (32, 32, 32, 32), "beta": 6.0,
+     "paper": {"device": "GeForce GTX 560 Ti (OpenCL)", "f32": 7.49e6, "f64": 3.58e6}},
+    {"group": 2, "dims": (44, 44, 44, 44), "beta": 2.3,
+     "paper": {"device": "GeForce GTX 560 Ti (OpenCL)", "f32": 1.58e7, "f64": 1.32e7}},
+]
+
+
+def run_paper_workloads(P, sweeps: int = 20):
+    out = []
+    for w in PAPER_TABLE1:
+        V = volume(w["dims"])
+        row = {"group": w["group"], "lattice": list(w["dims"]), "beta": w["beta"], "paper": w["paper"]}
+        for form, storage in (("f64", P.F64), ("f32", P.F32)):
+            lat = P.Lattice(w["group"], w["dims"], w["beta"], 0, storage=storage, rng=P.RNG_PHILOX, seed=5,
+                            start=P.HOT)
+            lat.run(3, 1, 0, measure_every=1)
+            lat.autotune(1, 0)
+            lat.run(1, 1, 0, measure_every=1)  # graph capture of the tuned shape
+            t0 = time.perf_counter()
+            lat.run(sweeps, 1, 0, measure_every=1)
+            rate = sweeps * 4 * V / (time.perf_counter() - t0)
+            lat.close()
+            row[form] = {"link_updates_per_s": rate, "ratio_to_paper": rate / w["paper"][form]}
+        log(f"[paper table 1] SU({w['group']}) {w['dims']}: F64 {row['f64']['link_updates_per_s']:.3e}, "
+            f"F32 {row['f32']['link_updates_per_s']:.3e} link updates/s")
+        out.append(row)
+    return out
+
+
 def cpu_baseline(steps: int):
     import oracle as O
     cores = len(os.sched_getaffinity(0))
@@ -444,6 +479,7 @@ def main() -> int:
     if not args.no_extras:
         out["su3_64x16"] = run_large(P)
         out["batch_64_lattices"] = run_batch(P, precision_sweeps=args.precision_sweeps)
+        out["paper_table1_workloads"] = run_paper_workloads(P)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
