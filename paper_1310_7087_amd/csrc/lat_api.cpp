@@ -171,6 +171,10 @@ int make_layout(int group, const int d[4], int storage, int rng, int layout, Lay
 
 }  // namespace
 
+// Results of HIP calls on clean-up paths (destroy, free) are ignored on
+// purpose: the handle is going away and an earlier error is already kept.
+inline void discard(hipError_t) {}
+
 struct lat_ctx {
     int group = 3, storage = LAT_F64, rng = LAT_RNG_PHILOX, start = LAT_HOT, nhit = 10, flux = 0;
     double beta = 0.0, rng_const = 0.5;
@@ -210,8 +214,8 @@ namespace {
 
 void drop_graphs(lat_ctx* h) {
     for (auto& kv : h->graphs) {
-        hipGraphExecDestroy(kv.second.second);
-        hipGraphDestroy(kv.second.first);
+        discard(hipGraphExecDestroy(kv.second.second));
+        discard(hipGraphDestroy(kv.second.first));
     }
     h->graphs.clear();
 }
@@ -289,14 +293,14 @@ int get_graph(lat_ctx* h, int n_hb, int n_or, hipGraphExec_t* out) {
     int rc = enqueue_sweep(h, n_hb, n_or);
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (rc != LAT_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) discard(hipGraphDestroy(graph));
         return rc;
     }
     if (e != hipSuccess) return fail(LAT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(graph);
+        discard(hipGraphDestroy(graph));
         return fail(LAT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     h->graphs[key] = std::make_pair(graph, exec);
@@ -454,11 +458,11 @@ int check_opts(const lat_options* o) {
 
 void destroy_handle(lat_ctx* h) {
     if (!h) return;
-    if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->stream) discard(hipStreamSynchronize(h->stream));
     drop_graphs(h);
-    if (h->accept_log) hipFree(h->accept_log);
-    if (h->own_mem && h->base) hipFree(h->base);
-    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    if (h->accept_log) discard(hipFree(h->accept_log));
+    if (h->own_mem && h->base) discard(hipFree(h->base));
+    if (h->own_stream && h->stream) discard(hipStreamDestroy(h->stream));
     delete h;
 }
 
@@ -631,7 +635,7 @@ int lat_get_links(lat_t h, double* host, size_t n_doubles) {
     hipError_t e = lat_launch_convert(h->group, h->storage, false, h->lay.g, tmp, h->links(), h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, n_doubles * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipFree(tmp);
+    discard(hipFree(tmp));
     if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_get_links: %s", hipGetErrorString(e));
     return LAT_OK;
 }
@@ -644,7 +648,7 @@ int lat_set_links(lat_t h, const double* host, size_t n_doubles) {
     hipError_t e = hipMemcpyAsync(tmp, host, n_doubles * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = lat_launch_convert(h->group, h->storage, true, h->lay.g, tmp, h->links(), h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipFree(tmp);
+    discard(hipFree(tmp));
     if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_set_links: %s", hipGetErrorString(e));
     return LAT_OK;
 }
@@ -711,7 +715,7 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
         sum_hb += t1;
         sum_or += t2;
     }
-    for (auto& e : ev) hipEventDestroy(e);
+    for (auto& e : ev) discard(hipEventDestroy(e));
     if (ms_hb) *ms_hb = n_hb ? sum_hb / (8.0 * n_hb * reps) : 0.0;
     if (ms_or) *ms_or = n_or ? sum_or / (8.0 * n_or * reps) : 0.0;
     return LAT_OK;
@@ -787,17 +791,17 @@ int time_compound(lat_ctx* h, const char* backup, int n_hb, int n_or, int reps, 
             rc = enqueue_sweep(h, n_hb, n_or);
             continue;
         }
-        hipEventRecord(e0, h->stream);
-        for (int r = 0; r < reps && !rc; ++r) rc = enqueue_sweep(h, n_hb, n_or);
-        hipEventRecord(e1, h->stream);
-        hipError_t e = hipEventSynchronize(e1);
+        hipError_t e = hipEventRecord(e0, h->stream);
+        for (int r = 0; r < reps && !rc && e == hipSuccess; ++r) rc = enqueue_sweep(h, n_hb, n_or);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
         float t = 0.f;
         if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
         if (!rc && e != hipSuccess) rc = fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
         if (!rc && t / reps < best) best = t / reps;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    discard(hipEventDestroy(e0));
+    discard(hipEventDestroy(e1));
     if (rc) return rc;
     *ms = best;
     return LAT_OK;
@@ -841,7 +845,7 @@ extern "C" int lat_autotune(lat_t h, int n_hb, int n_or, int result[3]) {
                 }
         hipError_t e = hipMemcpyAsync(h->base, backup, h->lay.total, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        hipFree(backup);
+        discard(hipFree(backup));
         h->hb_sweeps = hb0;
         h->sweeps = sw0;
         if (rc || e != hipSuccess || best.empty()) {
@@ -907,8 +911,8 @@ int lat_philox4x32_10(const uint32_t* ctr, const uint32_t key[2], uint32_t* out,
     if (e == hipSuccess) e = hipMemcpy(dc, ctr, n * 16, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = lat_launch_philox(dc, key[0], key[1], dout, (int64_t)n, nullptr);
     if (e == hipSuccess) e = hipMemcpy(out, dout, n * 16, hipMemcpyDeviceToHost);
-    hipFree(dc);
-    if (dout) hipFree(dout);
+    discard(hipFree(dc));
+    if (dout) discard(hipFree(dout));
     if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_philox4x32_10: %s", hipGetErrorString(e));
     return LAT_OK;
 }
@@ -1135,8 +1139,8 @@ int batch_build_table(lat_batch* b) {
 
 void batch_drop_graphs(lat_batch* b) {
     for (auto& kv : b->graphs) {
-        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+        if (kv.second.exec) discard(hipGraphExecDestroy(kv.second.exec));
+        if (kv.second.graph) discard(hipGraphDestroy(kv.second.graph));
     }
     b->graphs.clear();
 }
@@ -1168,12 +1172,12 @@ int batch_enqueue(lat_batch* b, int n_sweeps, int n_hb, int n_or) {
                                         b->grid, b->block, b->stream);
         hipError_t e2 = hipStreamEndCapture(b->stream, &g.graph);
         if (e != hipSuccess || e2 != hipSuccess) {
-            if (g.graph) hipGraphDestroy(g.graph);
+            if (g.graph) discard(hipGraphDestroy(g.graph));
             return fail(LAT_EDEVICE, "batch capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
         }
         e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            hipGraphDestroy(g.graph);
+            discard(hipGraphDestroy(g.graph));
             return fail(LAT_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(e));
         }
         it = b->graphs.emplace(key, g).first;
@@ -1316,9 +1320,12 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
                 b->spt = spts[si];
                 rc = batch_build_table(b);
                 if (rc) break;
-                hipEvent_t e0, e1;
-                hipEventCreate(&e0);
-                hipEventCreate(&e1);
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+                    if (e0) discard(hipEventDestroy(e0));
+                    rc = fail(LAT_EDEVICE, "autotune events");
+                    break;
+                }
                 // every trial starts from the saved members (the heat bath's
                 // cost depends on the links); the first also captures the graph
                 for (int trial = 0; trial < 3 && !rc; ++trial) {
@@ -1331,29 +1338,33 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
                         rc = batch_enqueue(b, 1, n_hb, n_or);
                         continue;
                     }
-                    hipEventRecord(e0, b->stream);
+                    if (hipEventRecord(e0, b->stream) != hipSuccess) {
+                        rc = fail(LAT_EDEVICE, "autotune timing");
+                        break;
+                    }
                     rc = batch_enqueue(b, 2, n_hb, n_or);
-                    hipEventRecord(e1, b->stream);
                     float t = 0.f;
-                    if (!rc && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess &&
-                        t / 2 < best_ms) {
+                    if (!rc && (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                        rc = fail(LAT_EDEVICE, "autotune timing");
+                    if (!rc && t / 2 < best_ms) {
                         best_ms = t / 2;
                         best = {blocks[bi], spts[si], 0};
                     }
                 }
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
+                discard(hipEventDestroy(e0));
+                discard(hipEventDestroy(e1));
             }
-        hipStreamSynchronize(b->stream);
+        if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = fail(LAT_EDEVICE, "autotune trials");
         for (size_t i = 0; i < b->members.size(); ++i) {
             if (!backup[i]) continue;
             lat_ctx* h = b->members[i];
             if (hipMemcpyAsync(h->base, backup[i], h->lay.total, hipMemcpyDeviceToDevice, b->stream) != hipSuccess && !rc)
                 rc = fail(LAT_EDEVICE, "autotune restore");
         }
-        hipStreamSynchronize(b->stream);
+        if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = fail(LAT_EDEVICE, "autotune restore");
         for (char* p : backup)
-            if (p) hipFree(p);
+            if (p) discard(hipFree(p));
         for (size_t i = 0; i < b->members.size(); ++i) {
             b->members[i]->hb_sweeps = counters[i].first;
             b->members[i]->sweeps = counters[i].second;
@@ -1409,13 +1420,13 @@ extern "C" int lat_batch_set_links(lat_batch_t b, int i, const double* host, siz
 
 extern "C" int lat_batch_destroy(lat_batch_t b) {
     if (!b) return LAT_OK;
-    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->stream) discard(hipStreamSynchronize(b->stream));
     batch_drop_graphs(b);
     for (lat_t h : b->members) lat_destroy(h);
-    if (b->d_lats) hipFree(b->d_lats);
-    if (b->d_counters) hipFree(b->d_counters);
-    if (b->d_work) hipFree(b->d_work);
-    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    if (b->d_lats) discard(hipFree(b->d_lats));
+    if (b->d_counters) discard(hipFree(b->d_counters));
+    if (b->d_work) discard(hipFree(b->d_work));
+    if (b->own_stream && b->stream) discard(hipStreamDestroy(b->stream));
     delete b;
     return LAT_OK;
 }
