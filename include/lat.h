@@ -182,7 +182,8 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
  * lattice, keeps the fastest, and restores the lattice's device state and
  * counters, so the Markov chain is unchanged (results do not depend on the
  * shape).  If the environment variable LAT_TUNE_CACHE names a file, choices
- * are read from and appended to it (key: group, extents, storage, device).
+ * are read from and added to it: a JSON object mapping a key (storage,
+ * group, extents, device) to the chosen shape, rewritten atomically.
  * result (optional) receives {work-group size, order, cap (-1 = none)}.
  * Synchronises.  LAT_ESTATE with the accept log on or an explicit 4-D tile.
  */

@@ -743,35 +743,79 @@ std::string tune_key(const char* what, const std::vector<int>& v, int storage) {
     return k + "_" + name;
 }
 
+// The tuning cache is a JSON object mapping each key to its chosen shape,
+// {"pass_s0_3_32_32_32_8_gfx950": [128, 0, 1], ...}, in the file named by
+// LAT_TUNE_CACHE (no cache if unset).  Only that flat form is read back;
+// anything else in the file is skipped.
+std::map<std::string, std::vector<int>> tune_cache_read(const char* path) {
+    std::map<std::string, std::vector<int>> m;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return m;
+    std::string t;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, n);
+    std::fclose(f);
+    size_t i = 0;
+    while (true) {
+        const size_t k0 = t.find('"', i);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = t.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const std::string key = t.substr(k0 + 1, k1 - k0 - 1);
+        const size_t lb = t.find('[', k1), rb = t.find(']', k1);
+        if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+        std::vector<int> v;
+        const char* c = t.c_str() + lb + 1;
+        const char* end = t.c_str() + rb;
+        while (c < end) {
+            char* e = nullptr;
+            const long x = std::strtol(c, &e, 10);
+            if (e == c) {
+                ++c;
+                continue;
+            }
+            v.push_back((int)x);
+            c = e;
+        }
+        m[key] = v;
+        i = rb + 1;
+    }
+    return m;
+}
+
 bool tune_cache_get(const std::string& key, std::vector<int>& val) {
     const char* path = std::getenv("LAT_TUNE_CACHE");
     if (!path || !*path) return false;
-    FILE* f = std::fopen(path, "r");
-    if (!f) return false;
-    char line[512];
-    bool found = false;
-    while (std::fgets(line, sizeof line, f)) {
-        char k[400];
-        int a = 0, b = 0, c = 0, n = std::sscanf(line, "%399s %d %d %d", k, &a, &b, &c);
-        if (n == 4 && key == k) {
-            val = {a, b, c};
-            found = true;  // the last entry for a key wins
-        }
-    }
-    std::fclose(f);
-    return found;
+    const auto m = tune_cache_read(path);
+    auto it = m.find(key);
+    if (it == m.end() || it->second.size() < 2) return false;
+    val = it->second;
+    while (val.size() < 3) val.push_back(0);
+    return true;
 }
 
 void tune_cache_put(const std::string& key, const std::vector<int>& val) {
     const char* path = std::getenv("LAT_TUNE_CACHE");
     if (!path || !*path) return;
-    FILE* f = std::fopen(path, "a");
+    auto m = tune_cache_read(path);
+    m[key] = val;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d\n", key.c_str(), val[0], val[1], val[2]);
-    std::fclose(f);
+    std::fprintf(f, "{");
+    bool first = true;
+    for (const auto& kv : m) {
+        std::fprintf(f, "%s\n  \"%s\": [", first ? "" : ",", kv.first.c_str());
+        for (size_t j = 0; j < kv.second.size(); ++j) std::fprintf(f, "%s%d", j ? ", " : "", kv.second[j]);
+        std::fprintf(f, "]");
+        first = false;
+    }
+    std::fprintf(f, "\n}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path);
 }
 
-// Time one compound sweep (average of `reps`) with the handle's current shape.
 // Time `reps` compound sweeps of the current launch shape.  Every trial
 // starts from the saved device state `backup`, so that all candidate shapes
 // are timed on the same links (the heat bath's cost depends on them); the

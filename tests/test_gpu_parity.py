@@ -388,7 +388,9 @@ def test_autotune_keeps_the_chain(tmp_path, monkeypatch):
         # a second tuner call is answered from the cache file
         c = P.Lattice(3, (16, 16, 16, 4), 5.9, seed=3, storage=storage)
         assert c.autotune(1, 4) == shape
-    assert (tmp_path / "tune.txt").read_text().count("\n") == 2
+    import json
+    cache = json.loads((tmp_path / "tune.txt").read_text())
+    assert len(cache) == 2 and all(len(v) == 3 for v in cache.values())
 
 
 def test_full_size_64x16_heat_bath_sweep(tmp_path, monkeypatch):
