@@ -66,6 +66,9 @@ extern "C" {
 #define LAT_RNG_PHILOX 1    /* per-site counter-based Philox4x32-10 */
 #define LAT_RNG_CONST 2     /* every uniform = rng_const (debugging, Sec. 3.4) */
 
+#define LAT_FROZEN_NONE 0  /* every link is updated */
+#define LAT_FROZEN_T0 1    /* spatial links at t = 0 held at the background */
+
 #define LAT_COLD 0  /* unit links */
 #define LAT_HOT 1   /* Haar-random links */
 
@@ -88,7 +91,7 @@ typedef struct {
                             state; it must stay alive until lat_destroy */
     size_t device_bytes; /* its size; see lat_device_bytes */
     int block_size;      /* work-group size of the sweep kernels: 0 = tuned
-                            default, else 64, 128, 256 or 512 */
+                            default, else 64, 128 or 256 */
     int tile_order;      /* work-group -> tile map: 0 = one z-slab per XCD (own
                             L2) when 8 | Nz, else identity (default); 1 = identity;
                             2 = reversed (order-independence tests);
@@ -102,6 +105,12 @@ typedef struct {
     int max_waves_per_simd; /* occupancy cap of the sweep kernels: 0 = default for
                             the form (1 for SU(3) FP64, whose staple traffic then
                             fits the L2 better; none otherwise), -1 = none, 1..8 */
+    int frozen;          /* LAT_FROZEN_NONE (default) or LAT_FROZEN_T0: the
+                            spatial links of the time slice t = 0 are set to the
+                            background field (U = 1, W = B) and never updated, so
+                            that the external field (Sec. 1, Sec. 3.2 "field
+                            flux") can no longer be removed by a change of
+                            variables; no random numbers are drawn for them */
 } lat_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -240,14 +249,14 @@ typedef struct {
  * and block_size (0 = tuned by lat_batch_autotune or the default); the
  * generator must be Philox (each member keyed by its own seed and
  * lattice_id); with LAT_F32_C12 (LAT_F64_C12) the SU(2) members use
- * LAT_F32 (LAT_F64); the
- * per-lattice fields of common are ignored.  Each member's
+ * LAT_F32 (LAT_F64); frozen links are not supported in a batch
+ * (LAT_EUNSUPPORTED); the per-lattice fields of common are ignored.  Each member's
  * results are bit-identical to the same lattice run alone. */
 int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common);
 /* Launch form and shape.  mode 0 (default): one kernel per pass index, each
  * covering that pass of every member (kernel boundaries order the passes);
- * mode 1: one persistent work-list kernel for all passes of the run, with
- * per-member dependency counters instead of any grid-wide barrier.
+ * mode 1, a persistent work-list kernel for all passes with per-member
+ * dependency counters, is switched off and returns LAT_EUNSUPPORTED.
  * block_size 64|128|256, sites_per_thread 1..8 per work item, grid = blocks
  * of the persistent kernel (0 = 1024 threads per compute unit).  Every form
  * and shape gives bit-identical results. */

@@ -45,7 +45,7 @@ def lib():
         vp, d, i, u32, u64, i64 = (ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64)
         L.orc_create.restype = vp
-        L.orc_create.argtypes = [i, i, i, i, i, d, i, i, d, u64, i, u32, i]
+        L.orc_create.argtypes = [i, i, i, i, i, d, i, i, d, u64, i, u32, i, i]
         L.orc_destroy.argtypes = [vp]
         L.orc_set_threads.argtypes = [i]
         L.orc_get_threads.restype = i
@@ -98,13 +98,14 @@ class Lattice:
     W-frame layout ``[site][mu][comp]``."""
 
     def __init__(self, group, dims, beta, flux=0, rng=RNG_PHILOX, rng_const=0.5,
-                 seed=1, nhit=10, lattice_id=0, start=HOT):
+                 seed=1, nhit=10, lattice_id=0, start=HOT, frozen=0):
         self.group = int(group)
         self.dims = tuple(int(x) for x in dims)
         self.V = int(np.prod(self.dims))
         self.rng = rng
         h = lib().orc_create(self.group, *self.dims, float(beta), int(flux), int(rng),
-                             float(rng_const), int(seed), int(nhit), int(lattice_id), int(start))
+                             float(rng_const), int(seed), int(nhit), int(lattice_id), int(start),
+                             int(frozen))
         if not h:
             raise ValueError("oracle rejected the lattice parameters")
         self._h = h

@@ -409,6 +409,7 @@ struct orc_lattice {
     uint64_t seed;
     int nhit;
     uint32_t lat_id;
+    int frozen;          // 1: spatial links of the slice t = 0 held at U = 1
     uint64_t hb_sweeps;  // heat-bath sweeps done so far (Philox counter word)
     std::vector<Mat> U;  // U-frame links, index i*4+mu
     std::vector<uint32_t> mrg;  // 6 words per site
@@ -552,7 +553,7 @@ static Mat from_canonical(int n, const double* in) {
 
 orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, int flux,
                         int rng, double rng_const, uint64_t seed, int nhit, uint32_t lattice_id,
-                        int start) {
+                        int start, int frozen) {
     int dims[4] = {nx, ny, nz, nt};
     if (group != 2 && group != 3) return nullptr;
     for (int m = 0; m < 4; ++m)
@@ -560,7 +561,9 @@ orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, 
     if (!(beta >= 0.0) || nhit < 1 || nhit > 127) return nullptr;
     if (rng < 0 || rng > 2) return nullptr;
     if (rng == ORC_RNG_MRG32K3A && (seed < 1 || seed >= MRG_M2)) return nullptr;
+    if (frozen != 0 && frozen != 1) return nullptr;
     orc_lattice* L = new orc_lattice();
+    L->frozen = frozen;
     L->n = group;
     for (int m = 0; m < 4; ++m) L->d[m] = dims[m];
     L->V = (int64_t)nx * ny * nz * nt;
@@ -607,6 +610,17 @@ orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, 
             }
         }
     }
+    // Frozen external field: the spatial links of the slice t = 0 are the
+    // background itself, W = B, i.e. U = 1 (their hot-start draws are made
+    // and discarded, so every other link sees the same random numbers).
+    if (frozen) {
+        for (int64_t i = 0; i < L->V; ++i) {
+            int x[4];
+            coords(L, i, x);
+            if (x[3] == 0)
+                for (int mu = 0; mu < 3; ++mu) L->U[i * 4 + mu] = mat_identity(group);
+        }
+    }
     return L;
 }
 
@@ -635,6 +649,7 @@ static void pass(orc_lattice* L, int mu, int p, int kind, bool reunit, int hb_in
     for (int64_t i = 0; i < L->V; ++i) {
         int x[4];
         coords(L, i, x);
+        if (L->frozen && mu < 3 && x[3] == 0) continue;  // held at the background, no draws
         if (((x[0] + x[1] + x[2] + x[3]) & 1) == p) sites.push_back(i);
     }
     const int64_t ns = (int64_t)sites.size();

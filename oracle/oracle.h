@@ -29,10 +29,14 @@ typedef struct orc_lattice orc_lattice;
 enum { ORC_RNG_MRG32K3A = 0, ORC_RNG_PHILOX = 1, ORC_RNG_CONST = 2 };
 enum { ORC_COLD = 0, ORC_HOT = 1 };
 
-/* Returns NULL on invalid arguments (odd or < 2 extents, group not 2/3). */
+/* Returns NULL on invalid arguments (odd or < 2 extents, group not 2/3).
+ * frozen = 1 holds the spatial links of the time slice t = 0 at the
+ * background field (U = 1, W = B) and never updates them: the external field
+ * of the paper's Sec. 1 can then no longer be removed by a change of
+ * variables (a reading: the paper names the field only as a flux). */
 orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta,
                         int flux, int rng, double rng_const, uint64_t seed,
-                        int nhit, uint32_t lattice_id, int start);
+                        int nhit, uint32_t lattice_id, int start, int frozen);
 void orc_destroy(orc_lattice* L);
 void orc_set_threads(int n);
 int  orc_get_threads(void);

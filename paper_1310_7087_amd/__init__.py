@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EIO, ECORRUPT, ESTATE, EUNSUPPORTED = 0, -1, -2, -3
 F64, F32, F32_C12, F64_C12 = 0, 1, 2, 3
 RNG_MRG32K3A, RNG_PHILOX, RNG_CONST = 0, 1, 2
 COLD, HOT = 0, 1
+FROZEN_NONE, FROZEN_T0 = 0, 1
 
 STORAGE_NAMES = {F64: "f64", F32: "f32", F32_C12: "f32c12", F64_C12: "f64c12"}
 
@@ -47,6 +48,7 @@ class Options(ctypes.Structure):
         ("layout", ctypes.c_int),
         ("tile", ctypes.c_int * 4),
         ("max_waves_per_simd", ctypes.c_int),
+        ("frozen", ctypes.c_int),
     ]
 
 
@@ -130,7 +132,7 @@ def default_options() -> Options:
 
 def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, nhit=10,
                  lattice_id=0, stream=None, device_buffer=None, block_size=0, tile_order=0,
-                 layout=0, tile=None, max_waves_per_simd=0) -> Options:
+                 layout=0, tile=None, max_waves_per_simd=0, frozen=0) -> Options:
     o = default_options()
     o.storage = storage
     o.rng = rng
@@ -143,6 +145,7 @@ def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, 
     o.tile_order = tile_order
     o.layout = layout
     o.max_waves_per_simd = max_waves_per_simd
+    o.frozen = frozen
     if tile is not None:
         for k in range(4):
             o.tile[k] = int(tile[k])

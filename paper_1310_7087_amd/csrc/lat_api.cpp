@@ -190,6 +190,7 @@ struct lat_ctx {
     int block = 256;
     int tile_order = 0;
     int meas_lds = 0;     // occupancy cap of the plaquette kernel (dynamic LDS bytes)
+    int frozen = 0;       // LAT_FROZEN_T0: spatial links at t = 0 are not updated
     int alternate = 1;    // odd-parity passes walk the z-slab order backwards
     int tshape[4] = {0, 0, 0, 0};
     int lds_reserve = 0;  // caps the waves per SIMD of the pass kernels
@@ -248,6 +249,7 @@ PassArgs pass_args(const lat_ctx* h) {
     a.zslab = 1;
     a.lds_reserve = h->lds_reserve;
     a.reverse = 0;
+    a.frozen = h->frozen;
     if (a.tile_order == 0) {
         // z-slabs per XCD need whole work-groups per z-plane and 8 | Nz
         const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
@@ -428,6 +430,7 @@ int init_handle(lat_ctx* h, const lat_options* opt) {
     ia.lat_id = h->lat_id;
     ia.start = h->start;
     ia.flux = h->flux;
+    ia.frozen = h->frozen;
     HIP_TRY(lat_launch_init(h->group, h->storage, h->rng, ia, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LAT_OK;
@@ -444,6 +447,7 @@ int check_opts(const lat_options* o) {
     if (o->tile_order < 0 || o->tile_order > 3) return fail(LAT_EINVAL, "tile_order must be 0..3");
     if (o->layout < 0 || o->layout > 1) return fail(LAT_EINVAL, "layout must be 0 or 1");
     if (o->max_waves_per_simd < -1 || o->max_waves_per_simd > 8) return fail(LAT_EINVAL, "max_waves_per_simd -1..8");
+    if (o->frozen != LAT_FROZEN_NONE && o->frozen != LAT_FROZEN_T0) return fail(LAT_EINVAL, "unknown frozen %d", o->frozen);
     if (o->tile[0] || o->tile[1] || o->tile[2] || o->tile[3]) {
         long prod = 1;
         for (int k = 0; k < 4; ++k) {
@@ -518,6 +522,7 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     h->start = o.start;
     h->nhit = o.nhit;
     h->flux = field_flux;
+    h->frozen = o.frozen;
     h->beta = beta;
     h->lat_id = o.lattice_id;
     h->block = o.block_size ? o.block_size : 256;
@@ -974,7 +979,7 @@ struct CkptHeader {
     char magic[8];
     uint32_t version, group, dims[4], storage, rng, start, nhit;
     int32_t flux;
-    uint32_t lat_id;
+    uint32_t lat_id, frozen, reserved;
     double beta, rng_const;
     uint64_t seed, hb_sweeps, sweeps, n_doubles, n_mrg;
 };
@@ -1004,7 +1009,7 @@ extern "C" int lat_save(lat_t h, const char* path) {
     CkptHeader hd;
     std::memset(&hd, 0, sizeof hd);
     std::memcpy(hd.magic, CKPT_MAGIC, 8);
-    hd.version = 1;
+    hd.version = 2;
     hd.group = (uint32_t)h->group;
     for (int m = 0; m < 4; ++m) hd.dims[m] = (uint32_t)h->dims[m];
     hd.storage = (uint32_t)h->storage;
@@ -1013,6 +1018,7 @@ extern "C" int lat_save(lat_t h, const char* path) {
     hd.nhit = (uint32_t)h->nhit;
     hd.flux = h->flux;
     hd.lat_id = h->lat_id;
+    hd.frozen = (uint32_t)h->frozen;
     hd.beta = h->beta;
     hd.rng_const = h->rng_const;
     hd.seed = h->seed;
@@ -1045,7 +1051,7 @@ extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
     FILE* f = std::fopen(path, "rb");
     if (!f) return fail(LAT_EIO, "cannot open %s", path);
     CkptHeader hd;
-    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0 || hd.version != 1) {
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0 || hd.version != 2) {
         std::fclose(f);
         return fail(LAT_ECORRUPT, "%s is not a lattice checkpoint", path);
     }
@@ -1079,6 +1085,7 @@ extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
     o.seed = hd.seed;
     o.nhit = (int)hd.nhit;
     o.lattice_id = hd.lat_id;
+    o.frozen = (int)hd.frozen;
     lat_t h = nullptr;
     int rc = lat_create(&h, (int)hd.group, (int)hd.dims[0], (int)hd.dims[1], (int)hd.dims[2], (int)hd.dims[3],
                         hd.beta, hd.flux, &o);
@@ -1258,6 +1265,7 @@ extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, cons
     lat_default_options(&o);
     if (common) o = *common;
     if (o.rng != LAT_RNG_PHILOX) return fail(LAT_EUNSUPPORTED, "batches use the Philox generator");
+    if (o.frozen != LAT_FROZEN_NONE) return fail(LAT_EUNSUPPORTED, "frozen links are not supported in a batch");
     lat_batch* b = new lat_batch();
     b->storage = o.storage;
     if (o.stream) {

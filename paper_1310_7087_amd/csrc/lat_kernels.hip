@@ -93,6 +93,7 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
     const coord4 c = decode(a.g, s, p);
+    if (a.frozen && mu < 3 && c.t == 0) return;  // held at the background field
     const coord4 cpm = step(a.g, c, mu, +1);
     const int64_t s_pm = half_index(a.g, cpm);
 
@@ -211,6 +212,7 @@ LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
     const coord4 c = decode(a.g, s, p);
+    if (a.frozen && mu < 3 && c.t == 0) return;  // held at the background field
     const coord4 cpm = step(a.g, c, mu, +1);
     const int64_t s_pm = half_index(a.g, cpm);
 
@@ -346,6 +348,7 @@ __global__ void __launch_bounds__(256) su3_init(InitArgs a) {
                 }
             reunit3(U);
         }
+        if (a.frozen && mu < 3 && c.t == 0) U = identity3<double>();  // W = B
         const double th = bg_theta(a.g, a.flux, c, mu);
         if (th != 0.0) {
             double sn, cs;
@@ -385,6 +388,7 @@ __global__ void __launch_bounds__(256) su2_init(InitArgs a) {
             const double nn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3]);
             U = {g[0] / nn, g[1] / nn, g[2] / nn, g[3] / nn};
         }
+        if (a.frozen && mu < 3 && c.t == 0) U = {1.0, 0.0, 0.0, 0.0};  // W = B
         const double th = bg_theta(a.g, a.flux, c, mu);
         if (th != 0.0) {
             double sn, cs;
@@ -764,6 +768,8 @@ LAT_DEV void batch_tile(const BatchArgs& b, int m, int tile, int64_t gp) {
     a.tcount[0] = a.tcount[1] = a.tcount[2] = a.tcount[3] = 1;
     a.nyb = a.zslab = 1;
     a.lds_reserve = 0;
+    a.reverse = 0;
+    a.frozen = 0;
     const int64_t end = (int64_t)(tile + 1) * b.tile < L.g.vh ? (int64_t)(tile + 1) * b.tile : L.g.vh;
     for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < end; s += blockDim.x)
         batch_site<ST3, ST2>(a, kind, reunit, s);

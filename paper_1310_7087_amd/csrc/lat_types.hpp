@@ -39,6 +39,7 @@ struct PassArgs {
     int nyb, zslab;        // z-slab order: work-groups per z-plane, z-planes per XCD
     int lds_reserve;       // dynamic LDS bytes reserved per work-group (caps occupancy)
     int reverse;           // z-slab order walked backwards (every other pass)
+    int frozen;            // 1: spatial links at t = 0 are not updated
 };
 
 // Initialisation of one lattice.
@@ -50,6 +51,7 @@ struct InitArgs {
     uint32_t key0, key1, lat_id;
     int start;  // 0 cold, 1 hot
     int flux;
+    int frozen;  // 1: spatial links at t = 0 start (and stay) at the background
 };
 
 // Reductions.

@@ -67,6 +67,7 @@ def test_device_bytes_layout():
     (2, (4, 4, 4, 4), 2.3, {"storage": 2}, -7),
     (2, (4, 4, 4, 4), 2.3, {"storage": 3}, -7),
     (3, (4, 4, 4, 4), 5.7, {"storage": 4}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"frozen": 2}, -1),
     (2, (4, 4, 4, 4), 2.3, {"rng": 0, "seed": 4294944443}, -1),
 ])
 def test_create_rejects_bad_arguments_without_a_device(group, dims, beta, kw, code):
@@ -109,3 +110,10 @@ def test_maximum_sizes():
     with pytest.raises(P.LatError) as e:
         P.Lattice(3, (256, 128, 128, 128), 6.0)
     assert e.value.code == P.EINVAL and "32-bit" in P.lib.lat_last_error().decode()
+
+
+def test_batch_rejects_frozen_links_without_a_device():
+    import paper_1310_7087_amd as P
+    with pytest.raises(P.LatError) as e:
+        P.Batch([dict(group=3, dims=(4, 4, 4, 4), beta=5.7)], frozen=P.FROZEN_T0)
+    assert e.value.code == P.EUNSUPPORTED

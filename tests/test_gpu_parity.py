@@ -27,11 +27,11 @@ TOL32 = 2e-5
 
 
 def pair(group, dims, beta, flux=0, rng=O.RNG_PHILOX, seed=1, start=O.HOT, storage=0, nhit=10,
-         rng_const=0.5, lattice_id=0, **kw):
+         rng_const=0.5, lattice_id=0, frozen=0, **kw):
     g = P.Lattice(group, dims, beta, flux, storage=storage, rng=rng, seed=seed, start=start, nhit=nhit,
-                  rng_const=rng_const, lattice_id=lattice_id, **kw)
+                  rng_const=rng_const, lattice_id=lattice_id, frozen=frozen, **kw)
     o = O.Lattice(group, dims, beta, flux=flux, rng=rng, seed=seed, start=start, nhit=nhit,
-                  rng_const=rng_const, lattice_id=lattice_id)
+                  rng_const=rng_const, lattice_id=lattice_id, frozen=frozen)
     return g, o
 
 
@@ -484,3 +484,42 @@ def test_graph_replays_equal_eager_launches(storage):
         pb, lb = b.measure()
         assert np.array_equal(pa, pb) and np.array_equal(la, lb)
     assert a.info() == b.info()
+
+
+@pytest.mark.parametrize("group,rng,start,sweeps", [
+    (3, O.RNG_PHILOX, O.COLD, [(1, 4), (2, 0)]),
+    (3, O.RNG_PHILOX, O.HOT, [(1, 0)]),
+    (2, O.RNG_MRG32K3A, O.COLD, [(1, 0)] * 10)])
+def test_frozen_background_links(group, rng, start, sweeps):
+    """Spatial links of the slice t = 0 held at the background (a
+    non-removable external field) against the oracle: every link, the
+    generator states (MRG32k3a draws nothing for a frozen link) and the
+    observables.  Sequences stay where the update map is well conditioned
+    (one compound sweep from cold, then heat-bath sweeps), as for the other
+    FP64 bars."""
+    dims = (8, 6, 4, 4)
+    beta = 5.7 if group == 3 else 2.3
+    g, o = pair(group, dims, beta, flux=2, rng=rng, seed=9, start=start, frozen=1)
+    t0 = np.arange(int(np.prod(dims))) // (dims[0] * dims[1] * dims[2]) == 0
+    before = g.get_links()
+    for h, r in sweeps:
+        g.sweep(h, r)
+        o.sweep(h, r)
+    after = g.get_links()
+    assert np.array_equal(after[t0, :3], before[t0, :3])
+    assert maxdiff(after, o.get_links()) < TOL64
+    if rng == O.RNG_MRG32K3A:
+        assert np.array_equal(g.rng_state(), o.mrg_states())
+    pg, lg = g.measure()
+    po, lo = o.measure()
+    assert maxdiff(pg, po) < TOL64 and maxdiff(lg, lo) < TOL64
+
+
+def test_frozen_flag_survives_a_checkpoint(tmp_path):
+    a = P.Lattice(3, (8, 6, 4, 4), 5.7, 2, seed=9, start=P.HOT, frozen=P.FROZEN_T0)
+    a.sweep(1, 2)
+    a.save(str(tmp_path / "f.ckpt"))
+    b = P.load_lattice(str(tmp_path / "f.ckpt"), 3, (8, 6, 4, 4))
+    a.sweep(1, 2)
+    b.sweep(1, 2)
+    assert np.array_equal(a.get_links(), b.get_links())
