@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-RNG_MRG32K3A, RNG_PHILOX, RNG_CONST = 0, 1, 2
+RNG_MRG32K3A, RNG_PHILOX, RNG_CONST, RNG_RANLUX = 0, 1, 2, 3
 COLD, HOT = 0, 1
 
 _lib = None
@@ -73,6 +73,10 @@ def lib():
         L.orc_update_link.argtypes = [i, d, i, i, i, vp, vp, vp, vp]
         L.orc_update_link.restype = i
         L.orc_staple.argtypes = [vp, i64, i, vp]
+        L.orc_ranlux_raw.argtypes = [u32, i, i, vp]
+        L.orc_ranlux_standard_values.argtypes = [vp]
+        L.orc_ranlux_site_seed.argtypes = [u64, i64, u32]
+        L.orc_ranlux_site_seed.restype = u32
         _lib = L
     return _lib
 
@@ -157,6 +161,24 @@ class Lattice:
         out = np.empty(2 * n * n)
         lib().orc_staple(self._h, int(site), int(mu), _ptr(out))
         return (out[0::2] + 1j * out[1::2]).reshape(n, n)
+
+
+def ranlux_raw(seed: int, n: int, luxury: bool = True) -> np.ndarray:
+    """First n 24-bit outputs of RANLUX luxury level 3 (p = 223, r = 24), or of
+    the bare subtract-with-borrow generator if luxury is False."""
+    out = np.empty(n, dtype=np.uint32)
+    lib().orc_ranlux_raw(int(seed), int(n), int(bool(luxury)), _ptr(out))
+    return out
+
+
+def ranlux_standard_values() -> tuple:
+    out = np.empty(2, dtype=np.uint32)
+    lib().orc_ranlux_standard_values(_ptr(out))
+    return int(out[0]), int(out[1])
+
+
+def ranlux_site_seed(seed: int, site: int, lattice_id: int = 0) -> int:
+    return int(lib().orc_ranlux_site_seed(int(seed), int(site), int(lattice_id)))
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:

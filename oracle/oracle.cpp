@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <complex>
+#include <random>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -279,6 +280,47 @@ struct MrgDraws : Draws {
         for (int k = 0; k < 2; ++k) u[k] = orc_uniform24(orc_mrg_next(st));
     }
 };
+/* RANLUX, luxury level 3 (Luscher 1994; James 1994): the subtract-with-
+ * borrow generator x_n = x_{n-10} - x_{n-24} - c mod 2^24 of which, in every
+ * block of p = 223 consecutive outputs, the first r = 24 are used and the
+ * rest discarded.  The C++ standard library defines both pieces
+ * (subtract_with_carry_engine<24, 10, 24> is ranlux24_base, and
+ * discard_block_engine takes p and r), so the oracle composes them. */
+typedef std::discard_block_engine<std::ranlux24_base, 223, 24> Ranlux3;
+/* Reading of the draw rule for RANLUX: every link update (and every link's
+ * hot-start draw) begins a new block of its site's stream; what the
+ * previous update left of its block is skipped.  A site's stream is seeded
+ * with 1 + (seed + 1000003 (i + 2654435761 lattice_id)) mod 2147483561. */
+struct RanluxSite {
+    Ranlux3 eng;
+    int used = 0;         // values drawn from the current block
+    bool claimed = false; // a block has been begun
+    void begin_update() {
+        if (claimed) eng.discard(24 - used);
+        used = 0;
+        claimed = true;
+    }
+    double next() {
+        if (used == 24) used = 0;  // an update that needs more runs into the next block
+        ++used;
+        return orc_uniform24((uint32_t)eng() << 8);
+    }
+};
+struct RanluxDraws : Draws {
+    RanluxSite* st;
+    void try4(int, int, double u[4]) override {
+        for (int k = 0; k < 4; ++k) u[k] = st->next();
+    }
+    void dir2(int, double u[2]) override {
+        for (int k = 0; k < 2; ++k) u[k] = st->next();
+    }
+};
+uint32_t ranlux_site_seed(uint64_t seed, int64_t i, uint32_t lattice_id) {
+    const uint64_t M = 2147483561ull;
+    const uint64_t j = ((uint64_t)i + 2654435761ull * (uint64_t)lattice_id) % M;
+    return (uint32_t)(1 + ((seed % M) + 1000003ull * j) % M);
+}
+
 struct ConstDraws : Draws {
     double c;
     void try4(int, int, double u[4]) override { u[0] = u[1] = u[2] = u[3] = c; }
@@ -413,6 +455,7 @@ struct orc_lattice {
     uint64_t hb_sweeps;  // heat-bath sweeps done so far (Philox counter word)
     std::vector<Mat> U;  // U-frame links, index i*4+mu
     std::vector<uint32_t> mrg;  // 6 words per site
+    std::vector<RanluxSite> ranlux;  // one stream per site
     bool log_accept = false;
     std::vector<int8_t> accept_log;  // [k][mu][i][g]
 };
@@ -559,7 +602,7 @@ orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, 
     for (int m = 0; m < 4; ++m)
         if (dims[m] < 2 || dims[m] % 2) return nullptr;
     if (!(beta >= 0.0) || nhit < 1 || nhit > 127) return nullptr;
-    if (rng < 0 || rng > 2) return nullptr;
+    if (rng < 0 || rng > 3) return nullptr;
     if (rng == ORC_RNG_MRG32K3A && (seed < 1 || seed >= MRG_M2)) return nullptr;
     if (frozen != 0 && frozen != 1) return nullptr;
     orc_lattice* L = new orc_lattice();
@@ -588,6 +631,10 @@ orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, 
             m33_vec(j2, st + 3, MRG_M2, st + 3);
         }
     }
+    if (rng == ORC_RNG_RANLUX) {
+        L->ranlux.resize(L->V);
+        for (int64_t i = 0; i < L->V; ++i) L->ranlux[i].eng.seed(ranlux_site_seed(seed, i, lattice_id));
+    }
     if (start == ORC_HOT) {
         int nu = group == 3 ? 12 : 4;
 #pragma omp parallel for schedule(static)
@@ -603,6 +650,9 @@ orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, 
                     }
                 } else if (rng == ORC_RNG_MRG32K3A) {
                     for (int k = 0; k < nu; ++k) u[k] = orc_uniform24(orc_mrg_next(&L->mrg[6 * i]));
+                } else if (rng == ORC_RNG_RANLUX) {
+                    L->ranlux[i].begin_update();
+                    for (int k = 0; k < nu; ++k) u[k] = L->ranlux[i].next();
                 } else {
                     for (int k = 0; k < nu; ++k) u[k] = rng_const;
                 }
@@ -660,6 +710,7 @@ static void pass(orc_lattice* L, int mu, int p, int kind, bool reunit, int hb_in
         Mat M = mat_mul(n, wlink(L, i, mu), A);
         PhiloxDraws pd;
         MrgDraws md;
+        RanluxDraws rd;
         ConstDraws cd;
         Draws* d;
         if (L->rng == ORC_RNG_PHILOX) {
@@ -673,6 +724,10 @@ static void pass(orc_lattice* L, int mu, int p, int kind, bool reunit, int hb_in
         } else if (L->rng == ORC_RNG_MRG32K3A) {
             md.st = &L->mrg[6 * i];
             d = &md;
+        } else if (L->rng == ORC_RNG_RANLUX) {
+            rd.st = &L->ranlux[i];
+            if (kind == 0) rd.st->begin_update();
+            d = &rd;
         } else {
             cd.c = L->rng_const;
             d = &cd;
@@ -775,6 +830,29 @@ void orc_set_links(orc_lattice* L, const double* in) {
 }
 
 uint64_t orc_hb_sweeps(const orc_lattice* L) { return L->hb_sweeps; }
+
+void orc_ranlux_raw(uint32_t seed, int n, int luxury_blocks, uint32_t* out) {
+    if (luxury_blocks) {
+        Ranlux3 e(seed);
+        for (int k = 0; k < n; ++k) out[k] = (uint32_t)e();
+    } else {
+        std::ranlux24_base e(seed);
+        for (int k = 0; k < n; ++k) out[k] = (uint32_t)e();
+    }
+}
+
+void orc_ranlux_standard_values(uint32_t out[2]) {
+    std::ranlux24_base a;
+    std::ranlux24 b;
+    a.discard(9999);
+    b.discard(9999);
+    out[0] = (uint32_t)a();
+    out[1] = (uint32_t)b();
+}
+
+uint32_t orc_ranlux_site_seed(uint64_t seed, int64_t i, uint32_t lattice_id) {
+    return ranlux_site_seed(seed, i, lattice_id);
+}
 
 int orc_get_mrg_states(const orc_lattice* L, uint32_t* out) {
     if (L->rng != ORC_RNG_MRG32K3A) return -1;

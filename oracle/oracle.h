@@ -26,7 +26,7 @@ extern "C" {
 
 typedef struct orc_lattice orc_lattice;
 
-enum { ORC_RNG_MRG32K3A = 0, ORC_RNG_PHILOX = 1, ORC_RNG_CONST = 2 };
+enum { ORC_RNG_MRG32K3A = 0, ORC_RNG_PHILOX = 1, ORC_RNG_CONST = 2, ORC_RNG_RANLUX = 3 };
 enum { ORC_COLD = 0, ORC_HOT = 1 };
 
 /* Returns NULL on invalid arguments (odd or < 2 extents, group not 2/3).
@@ -53,6 +53,14 @@ void orc_set_links(orc_lattice* L, const double* in);
 uint64_t orc_hb_sweeps(const orc_lattice* L);
 /* MRG32k3a per-site states, 6 words per site (x1[n-3],x1[n-2],x1[n-1],x2[...]). */
 int  orc_get_mrg_states(const orc_lattice* L, uint32_t* out);
+/* RANLUX luxury level 3 (p = 223, r = 24) raw 24-bit outputs for one seed
+ * (luxury_blocks = 0: the bare subtract-with-borrow base generator). */
+void orc_ranlux_raw(uint32_t seed, int n, int luxury_blocks, uint32_t* out);
+/* The 10000th outputs of default-seeded ranlux24_base and ranlux24 as
+ * computed by this C++ library (the standard fixes 7937952 and 9901578). */
+void orc_ranlux_standard_values(uint32_t out[2]);
+/* Seed of site i's RANLUX stream. */
+uint32_t orc_ranlux_site_seed(uint64_t seed, int64_t i, uint32_t lattice_id);
 /* Accept log of the most recent compound sweep's heat-bath updates:
  * one int8 per (hb sweep k, mu, site i, subgroup g), value = accepted try
  * index or -1.  Layout [k][mu][i][g], g < 3.  Enabled by orc_enable_accept_log. */
