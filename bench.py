@@ -300,8 +300,9 @@ def cpu_model() -> str:
 
 
 # The paper's Table 1 working sweeps (one heat-bath sweep with NHIT = 10 and
-# reunitarisation, plus the measurement; Haar start), with the link-update
-# rates derived from its seconds per sweep on its own 2011 GPUs: context only.
+# reunitarisation, plus the measurement; Haar start; RANLUX luxury level 3
+# streams as in the paper, Philox beside them), with the link-update rates
+# derived from its seconds per sweep on its own 2011 GPUs: context only.
 PAPER_TABLE1 = [
     {"group": 3, "dims": (32, 32, 32, 32), "beta": 6.0,
      "paper": {"device": "GeForce GTX 560 Ti (OpenCL)", "f32": 7.49e6, "f64": 3.58e6}},
@@ -316,17 +317,20 @@ def run_paper_workloads(P, sweeps: int = 20):
         V = volume(w["dims"])
         row = {"group": w["group"], "lattice": list(w["dims"]), "beta": w["beta"], "paper": w["paper"]}
         for form, storage in (("f64", P.F64), ("f32", P.F32)):
-            lat = P.Lattice(w["group"], w["dims"], w["beta"], 0, storage=storage, rng=P.RNG_PHILOX, seed=5,
-                            start=P.HOT)
-            lat.run(3, 1, 0, measure_every=1)
-            lat.autotune(1, 0)
-            lat.run(1, 1, 0, measure_every=1)  # graph capture of the tuned shape
-            t0 = time.perf_counter()
-            lat.run(sweeps, 1, 0, measure_every=1)
-            rate = sweeps * 4 * V / (time.perf_counter() - t0)
-            lat.close()
-            row[form] = {"link_updates_per_s": rate, "ratio_to_paper": rate / w["paper"][form]}
-        log(f"[paper table 1] SU({w['group']}) {w['dims']}: F64 {row['f64']['link_updates_per_s']:.3e}, "
+            rates = {}
+            for gen, rng in (("ranlux", P.RNG_RANLUX), ("philox", P.RNG_PHILOX)):
+                lat = P.Lattice(w["group"], w["dims"], w["beta"], 0, storage=storage, rng=rng, seed=5,
+                                start=P.HOT)
+                lat.run(3, 1, 0, measure_every=1)
+                lat.autotune(1, 0)
+                lat.run(1, 1, 0, measure_every=1)  # graph capture of the tuned shape
+                t0 = time.perf_counter()
+                lat.run(sweeps, 1, 0, measure_every=1)
+                rates[gen] = sweeps * 4 * V / (time.perf_counter() - t0)
+                lat.close()
+            row[form] = {"link_updates_per_s": rates["ranlux"], "ratio_to_paper": rates["ranlux"] / w["paper"][form],
+                         "philox_link_updates_per_s": rates["philox"]}
+        log(f"[paper table 1] SU({w['group']}) {w['dims']} RANLUX: F64 {row['f64']['link_updates_per_s']:.3e}, "
             f"F32 {row['f32']['link_updates_per_s']:.3e} link updates/s")
         out.append(row)
     return out

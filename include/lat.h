@@ -65,6 +65,14 @@ extern "C" {
 #define LAT_RNG_MRG32K3A 0  /* per-site MRG32k3a streams, 2^127 apart */
 #define LAT_RNG_PHILOX 1    /* per-site counter-based Philox4x32-10 */
 #define LAT_RNG_CONST 2     /* every uniform = rng_const (debugging, Sec. 3.4) */
+#define LAT_RNG_RANLUX 3    /* per-site RANLUX, luxury level 3 (the generator of the
+                               paper's benchmark runs, Sec. 5): of every 223 outputs
+                               of the subtract-with-borrow generator x_n = x_{n-10}
+                               - x_{n-24} - c mod 2^24 the first 24 are used; site i
+                               is seeded with 1 + (seed + 1000003 (i + 2654435761
+                               lattice_id)) mod 2147483561 by the standard
+                               40014-multiplier procedure; each link update begins
+                               a new block of 24 */
 
 #define LAT_FROZEN_NONE 0  /* every link is updated */
 #define LAT_FROZEN_T0 1    /* spatial links at t = 0 held at the background */
@@ -77,7 +85,8 @@ typedef struct lat_batch* lat_batch_t;
 
 typedef struct {
     int storage;         /* LAT_F64 (default), LAT_F32, LAT_F32_C12, LAT_F64_C12 */
-    int rng;             /* LAT_RNG_PHILOX (default), LAT_RNG_MRG32K3A, LAT_RNG_CONST */
+    int rng;             /* LAT_RNG_PHILOX (default), LAT_RNG_MRG32K3A, LAT_RNG_CONST,
+                            LAT_RNG_RANLUX */
     double rng_const;    /* value of every uniform for LAT_RNG_CONST, in (0,1) */
     int start;           /* LAT_HOT (default) or LAT_COLD */
     uint64_t seed;       /* run seed; 0 = derived from the system time and reported
@@ -167,9 +176,11 @@ int lat_measure(lat_t h, double plaq[3], double poly[2]);
 int lat_get_links(lat_t h, double* host, size_t n_doubles);
 /* Replaces all links (rounded to the storage form; 12-real keeps rows 1-2). */
 int lat_set_links(lat_t h, const double* host, size_t n_doubles);
-/* MRG32k3a per-site states in canonical site order, 6 words per site
- * (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1]); n_words = 6*V.
- * LAT_ESTATE for other generators. */
+/* Per-site generator states in canonical site order: MRG32k3a 6 words per
+ * site (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1]); RANLUX 25
+ * words per site (the last delivered block of 24 subtract-with-borrow
+ * outputs, oldest first, then carry | 2 while no block has been delivered);
+ * n_words = words * V.  LAT_ESTATE for the stateless generators. */
 int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words);
 /*
  * Kernel profiling (the paper's run-time kernel profiling, Sec. 3.2): runs

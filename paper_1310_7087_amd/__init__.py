@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "liblat.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EIO, ECORRUPT, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F32_C12, F64_C12 = 0, 1, 2, 3
-RNG_MRG32K3A, RNG_PHILOX, RNG_CONST = 0, 1, 2
+RNG_MRG32K3A, RNG_PHILOX, RNG_CONST, RNG_RANLUX = 0, 1, 2, 3
 COLD, HOT = 0, 1
 FROZEN_NONE, FROZEN_T0 = 0, 1
 
@@ -173,10 +173,12 @@ class Lattice:
         self.dims = tuple(int(x) for x in dims)
         self.V = int(np.prod(self.dims))
         self._keep = keepalive
+        self.rng = RNG_PHILOX
         if _handle is not None:
             self._h = _handle
             return
         o = make_options(**opts)
+        self.rng = int(o.rng)
         if "device_buffer" in opts and opts["device_buffer"] is not None:
             self._keep = opts["device_buffer"]
         h = ctypes.c_void_p()
@@ -223,7 +225,9 @@ class Lattice:
         _check(lib.lat_set_links(self._h, _ptr(a), a.size))
 
     def rng_state(self) -> np.ndarray:
-        out = np.empty((self.V, 6), dtype=np.uint32)
+        """Per-site generator state words (MRG32k3a: 6, RANLUX: 25)."""
+        words = {RNG_MRG32K3A: 6, RNG_RANLUX: 25}.get(self.rng, 6)
+        out = np.empty((self.V, words), dtype=np.uint32)
         _check(lib.lat_get_rng_state(self._h, _ptr(out), out.size))
         return out
 

@@ -75,6 +75,31 @@ void mod3_apply(const Mod3& x, uint32_t* v, uint64_t m) {
     for (int i = 0; i < 3; ++i) v[i] = (uint32_t)r[i];
 }
 // Per-site stream states: site i starts at A^(i * 2^127) (s,s,s,s,s,s).
+// 32-bit words of per-site generator state: MRG32k3a 6, RANLUX 24 + 1
+// (the last delivered block of the subtract-with-borrow generator, oldest
+// first, then carry | 2 while the first block is still to come).
+int rng_words(int rng) { return rng == LAT_RNG_MRG32K3A ? 6 : rng == LAT_RNG_RANLUX ? 25 : 0; }
+
+// Seed of site i's RANLUX stream, then the standard seeding of the
+// subtract-with-borrow generator: a Lehmer generator x -> 40014 x mod
+// 2147483563 started at the seed gives the 24 initial words (mod 2^24,
+// oldest first); the carry starts at 1 if the newest word is 0.
+std::vector<uint32_t> ranlux_site_states(uint64_t seed, uint32_t lattice_id, int64_t nsites) {
+    const uint64_t M = 2147483561ull;
+    std::vector<uint32_t> out((size_t)nsites * 25);
+    for (int64_t i = 0; i < nsites; ++i) {
+        const uint64_t j = ((uint64_t)i + 2654435761ull * (uint64_t)lattice_id) % M;
+        uint64_t e = 1 + ((seed % M) + 1000003ull * j) % M;
+        uint32_t* w = &out[(size_t)i * 25];
+        for (int k = 0; k < 24; ++k) {
+            e = (40014ull * e) % 2147483563ull;
+            w[k] = (uint32_t)(e & 0xFFFFFFu);
+        }
+        w[24] = (w[23] == 0 ? 1u : 0u) | 2u;
+    }
+    return out;
+}
+
 std::vector<uint32_t> mrg_site_states(uint64_t seed, int64_t nsites) {
     Mod3 j1 = {{{0, 1, 0}, {0, 0, 1}, {MRG_M1 - 810728u, 1403580u, 0}}};
     Mod3 j2 = {{{0, 1, 0}, {0, 0, 1}, {MRG_M2 - 1370589u, 0, 527612u}}};
@@ -150,7 +175,7 @@ int make_layout(int group, const int d[4], int storage, int rng, int layout, Lay
     L.links_bytes = (size_t)g.vh_pad * 2 * 4 * bytes_per_link(group, storage);
     size_t off = align_up(L.links_bytes, 4096);
     L.mrg_off = off;
-    L.mrg_bytes = rng == LAT_RNG_MRG32K3A ? (size_t)g.vh_pad * 2 * 6 * 4 : 0;
+    L.mrg_bytes = (size_t)g.vh_pad * 2 * rng_words(rng) * 4;
     off = align_up(off + L.mrg_bytes, 256);
     L.hb_off = off;
     off += 256;
@@ -402,11 +427,13 @@ int init_handle(lat_ctx* h, const lat_options* opt) {
     // counters start at zero
     std::vector<uint8_t> zero(512, 0);
     HIP_TRY(hipMemcpyAsync(h->base + h->lay.hb_off, zero.data(), 512, hipMemcpyHostToDevice, h->stream));
-    if (h->rng == LAT_RNG_MRG32K3A) {
+    if (rng_words(h->rng)) {
         // canonical per-site states -> [parity][word][half index]
-        std::vector<uint32_t> canon = mrg_site_states(h->seed, h->V());
+        const int W = rng_words(h->rng);
+        std::vector<uint32_t> canon = h->rng == LAT_RNG_MRG32K3A ? mrg_site_states(h->seed, h->V())
+                                                                 : ranlux_site_states(h->seed, h->lat_id, h->V());
         const LatGeom& g = h->lay.g;
-        std::vector<uint32_t> dev((size_t)g.vh_pad * 12, 0);
+        std::vector<uint32_t> dev((size_t)g.vh_pad * 2 * W, 0);
         for (int64_t i = 0; i < h->V(); ++i) {
             int64_t r = i;
             const int x = (int)(r % g.nx); r /= g.nx;
@@ -415,7 +442,7 @@ int init_handle(lat_ctx* h, const lat_options* opt) {
             const int t = (int)(r / g.nz);
             const int p = (x + y + z + t) & 1;
             const int64_t s = (x >> 1) + (int64_t)g.nxh * (y + (int64_t)g.ny * (z + (int64_t)g.nz * t));
-            for (int w = 0; w < 6; ++w) dev[((size_t)p * 6 + w) * g.vh_pad + s] = canon[(size_t)i * 6 + w];
+            for (int w = 0; w < W; ++w) dev[((size_t)p * W + w) * g.vh_pad + s] = canon[(size_t)i * W + w];
         }
         HIP_TRY(hipMemcpyAsync(h->mrg(), dev.data(), dev.size() * 4, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -437,7 +464,7 @@ int init_handle(lat_ctx* h, const lat_options* opt) {
 }
 
 int check_opts(const lat_options* o) {
-    if (o->rng < LAT_RNG_MRG32K3A || o->rng > LAT_RNG_CONST) return fail(LAT_EINVAL, "unknown rng %d", o->rng);
+    if (o->rng < LAT_RNG_MRG32K3A || o->rng > LAT_RNG_RANLUX) return fail(LAT_EINVAL, "unknown rng %d", o->rng);
     if (o->rng == LAT_RNG_CONST && !(o->rng_const > 0.0 && o->rng_const < 1.0))
         return fail(LAT_EINVAL, "rng_const must lie in (0,1)");
     if (o->start != LAT_COLD && o->start != LAT_HOT) return fail(LAT_EINVAL, "unknown start %d", o->start);
@@ -660,10 +687,11 @@ int lat_set_links(lat_t h, const double* host, size_t n_doubles) {
 
 int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words) {
     if (!h || !host) return fail(LAT_EINVAL, "NULL argument");
-    if (h->rng != LAT_RNG_MRG32K3A) return fail(LAT_ESTATE, "generator has no per-site state");
-    if (n_words != (size_t)h->V() * 6) return fail(LAT_EINVAL, "need %lld words", (long long)(h->V() * 6));
+    const int W = rng_words(h->rng);
+    if (!W) return fail(LAT_ESTATE, "generator has no per-site state");
+    if (n_words != (size_t)h->V() * W) return fail(LAT_EINVAL, "need %lld words", (long long)(h->V() * W));
     const LatGeom& g = h->lay.g;
-    std::vector<uint32_t> dev((size_t)g.vh_pad * 12);
+    std::vector<uint32_t> dev((size_t)g.vh_pad * 2 * W);
     HIP_TRY(hipMemcpyAsync(dev.data(), h->mrg(), dev.size() * 4, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (int64_t i = 0; i < h->V(); ++i) {
@@ -674,7 +702,7 @@ int lat_get_rng_state(lat_t h, uint32_t* host, size_t n_words) {
         const int t = (int)(r / g.nz);
         const int p = (x + y + z + t) & 1;
         const int64_t s = (x >> 1) + (int64_t)g.nxh * (y + (int64_t)g.ny * (z + (int64_t)g.nz * t));
-        for (int w = 0; w < 6; ++w) host[(size_t)i * 6 + w] = dev[((size_t)p * 6 + w) * g.vh_pad + s];
+        for (int w = 0; w < W; ++w) host[(size_t)i * W + w] = dev[((size_t)p * W + w) * g.vh_pad + s];
     }
     return LAT_OK;
 }
@@ -1001,8 +1029,8 @@ extern "C" int lat_save(lat_t h, const char* path) {
     int rc = lat_get_links(h, links.data(), links.size());
     if (rc) return rc;
     std::vector<uint32_t> mrg;
-    if (h->rng == LAT_RNG_MRG32K3A) {
-        mrg.resize((size_t)h->V() * 6);
+    if (rng_words(h->rng)) {
+        mrg.resize((size_t)h->V() * rng_words(h->rng));
         rc = lat_get_rng_state(h, mrg.data(), mrg.size());
         if (rc) return rc;
     }
@@ -1057,7 +1085,7 @@ extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
     }
     const uint64_t V = (uint64_t)hd.dims[0] * hd.dims[1] * hd.dims[2] * hd.dims[3];
     if ((hd.group != 2 && hd.group != 3) || hd.n_doubles != V * 4 * (uint64_t)ncomp((int)hd.group) ||
-        (hd.n_mrg != 0 && hd.n_mrg != V * 6)) {
+        hd.rng > (uint32_t)LAT_RNG_RANLUX || hd.n_mrg != V * (uint64_t)rng_words((int)hd.rng)) {
         std::fclose(f);
         return fail(LAT_ECORRUPT, "inconsistent checkpoint header in %s", path);
     }
@@ -1094,7 +1122,8 @@ extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
     rc = lat_set_links(h, links.data(), links.size());
     if (!rc && !mrg.empty()) {
         const LatGeom& g = h->lay.g;
-        std::vector<uint32_t> dev((size_t)g.vh_pad * 12, 0);
+        const int W = rng_words(h->rng);
+        std::vector<uint32_t> dev((size_t)g.vh_pad * 2 * W, 0);
         for (int64_t i = 0; i < h->V(); ++i) {
             int64_t r = i;
             const int x = (int)(r % g.nx); r /= g.nx;
@@ -1103,7 +1132,7 @@ extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
             const int t = (int)(r / g.nz);
             const int p = (x + y + z + t) & 1;
             const int64_t s = (x >> 1) + (int64_t)g.nxh * (y + (int64_t)g.ny * (z + (int64_t)g.nz * t));
-            for (int w = 0; w < 6; ++w) dev[((size_t)p * 6 + w) * g.vh_pad + s] = mrg[(size_t)i * 6 + w];
+            for (int w = 0; w < W; ++w) dev[((size_t)p * W + w) * g.vh_pad + s] = mrg[(size_t)i * W + w];
         }
         hipError_t e = hipMemcpy(h->mrg(), dev.data(), dev.size() * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = fail(LAT_EDEVICE, "restore of generator state: %s", hipGetErrorString(e));

@@ -345,6 +345,70 @@ struct draws<LAT_RNG_MRG_I> {
         D[1] = u24(mrg_step(st));
     }
 };
+// RANLUX, luxury level 3: subtract-with-borrow x_n = x_{n-10} - x_{n-24} - c
+// mod 2^24; of every 223 outputs the first 24 are used.  b[24] holds the
+// last 24 outputs oldest first, so one in-place round of 24 steps reads
+// x_{n-10} at b[(k+14) % 24] (an old value for k < 10, a new one after) and
+// x_{n-24} at b[k], and leaves b oldest first again.
+LAT_DEV void swb_round(uint32_t (&b)[24], uint32_t& c) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        const int32_t y = (int32_t)b[(k + 14) % 24] - (int32_t)b[k] - (int32_t)c;
+        c = y < 0 ? 1u : 0u;
+        b[k] = (uint32_t)y & 0xFFFFFFu;
+    }
+}
+// From the last delivered block to the next one: skip the other 199 outputs
+// of the current group of 223 (8 rounds and 7 steps, after which b is
+// rotated back to oldest first), then one round gives the 24 next outputs.
+// The first block after seeding follows the seed words directly.
+LAT_DEV void ranlux_next_block(uint32_t (&b)[24], uint32_t& c, bool skip) {
+    if (skip) {
+        for (int r = 0; r < 8; ++r) swb_round(b, c);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int32_t y = (int32_t)b[k + 14] - (int32_t)b[k] - (int32_t)c;
+            c = y < 0 ? 1u : 0u;
+            b[k] = (uint32_t)y & 0xFFFFFFu;
+        }
+        uint32_t t[24];
+#pragma unroll
+        for (int j = 0; j < 24; ++j) t[j] = b[(j + 7) % 24];
+#pragma unroll
+        for (int j = 0; j < 24; ++j) b[j] = t[j];
+    }
+    swb_round(b, c);
+}
+// The current block lives in LDS (word j of this thread at lds[j * stride])
+// because draws index it with a per-lane position; a link update that
+// needs more than 24 values moves on to the next block.
+template <>
+struct draws<LAT_RNG_RANLUX_I> {
+    uint32_t* lds;
+    int stride;
+    uint32_t c;
+    int idx;
+    LAT_DEV uint32_t next() {
+        if (idx == 24) {
+            uint32_t b[24];
+#pragma unroll
+            for (int j = 0; j < 24; ++j) b[j] = lds[j * stride];
+            ranlux_next_block(b, c, true);
+#pragma unroll
+            for (int j = 0; j < 24; ++j) lds[j * stride] = b[j];
+            idx = 0;
+        }
+        return lds[(idx++) * stride];
+    }
+    LAT_DEV void try4(int, int, double R[4]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) R[k] = u24(next() << 8);
+    }
+    LAT_DEV void dir2(int, double D[2]) {
+        D[0] = u24(next() << 8);
+        D[1] = u24(next() << 8);
+    }
+};
 template <>
 struct draws<LAT_RNG_CONST_I> {
     double c;

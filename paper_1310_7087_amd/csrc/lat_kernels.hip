@@ -89,6 +89,7 @@ template <class ST, int KIND, bool REUNIT, int RNG, int MU = -1>
 LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     using T = typename ST::real;
     using M = m3<T>;
+    __shared__ uint32_t rl_lds[RNG == LAT_RNG_RANLUX_I ? 24 * 256 : 1];  // current RANLUX block
     const int p = a.parity, q = 1 - p, mu = MU >= 0 ? MU : a.mu;
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
@@ -111,11 +112,26 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
         } else if constexpr (RNG == LAT_RNG_MRG_I) {
 #pragma unroll
             for (int w = 0; w < 6; ++w) d.st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+        } else if constexpr (RNG == LAT_RNG_RANLUX_I) {
+            // every link update begins a new block of the site's stream
+            uint32_t b[24];
+#pragma unroll
+            for (int j = 0; j < 24; ++j) b[j] = a.mrg[((int64_t)p * 25 + j) * vp + s];
+            const uint32_t f = a.mrg[((int64_t)p * 25 + 24) * vp + s];
+            uint32_t cy = f & 1u;
+            ranlux_next_block(b, cy, (f & 2u) == 0);
+            d.lds = rl_lds + threadIdx.x;
+            d.stride = (int)blockDim.x;
+#pragma unroll
+            for (int j = 0; j < 24; ++j) d.lds[j * d.stride] = b[j];
+            d.c = cy;
+            d.idx = 0;
         } else {
             d.c = a.rng_const;
         }
     }
-    constexpr bool PREPARE = (KIND == 0 && RNG != LAT_RNG_MRG_I);
+    // counter-addressed and constant draws do not depend on earlier tries
+    constexpr bool PREPARE = (KIND == 0 && (RNG == LAT_RNG_PHILOX_I || RNG == LAT_RNG_CONST_I));
     kp_first first[3];
 
     // staple A = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
@@ -192,6 +208,11 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
 #pragma unroll
         for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = d.st.s[w];
     }
+    if constexpr (KIND == 0 && RNG == LAT_RNG_RANLUX_I) {
+#pragma unroll
+        for (int j = 0; j < 24; ++j) a.mrg[((int64_t)p * 25 + j) * vp + s] = d.lds[j * d.stride];
+        a.mrg[((int64_t)p * 25 + 24) * vp + s] = d.c;  // a block has been delivered
+    }
 }
 
 template <class ST, int KIND, bool REUNIT, int RNG, int MU>
@@ -208,6 +229,7 @@ template <class ST, int KIND, bool REUNIT, int RNG>
 LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
     using T = typename ST::real;
     using Q = qt<T>;
+    __shared__ uint32_t rl_lds[RNG == LAT_RNG_RANLUX_I ? 24 * 256 : 1];  // current RANLUX block
     const int p = a.parity, q = 1 - p, mu = a.mu;
     const int64_t vp = a.g.vh_pad;
     const char* L = a.links;
@@ -249,6 +271,19 @@ LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
         } else if constexpr (RNG == LAT_RNG_MRG_I) {
 #pragma unroll
             for (int w = 0; w < 6; ++w) d.st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
+        } else if constexpr (RNG == LAT_RNG_RANLUX_I) {
+            uint32_t b[24];
+#pragma unroll
+            for (int j = 0; j < 24; ++j) b[j] = a.mrg[((int64_t)p * 25 + j) * vp + s];
+            const uint32_t f = a.mrg[((int64_t)p * 25 + 24) * vp + s];
+            uint32_t cy = f & 1u;
+            ranlux_next_block(b, cy, (f & 2u) == 0);
+            d.lds = rl_lds + threadIdx.x;
+            d.stride = (int)blockDim.x;
+#pragma unroll
+            for (int j = 0; j < 24; ++j) d.lds[j * d.stride] = b[j];
+            d.c = cy;
+            d.idx = 0;
         } else {
             d.c = a.rng_const;
         }
@@ -269,6 +304,11 @@ LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
         if constexpr (RNG == LAT_RNG_MRG_I) {
 #pragma unroll
             for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = d.st.s[w];
+        }
+        if constexpr (RNG == LAT_RNG_RANLUX_I) {
+#pragma unroll
+            for (int j = 0; j < 24; ++j) a.mrg[((int64_t)p * 25 + j) * vp + s] = d.lds[j * d.stride];
+            a.mrg[((int64_t)p * 25 + 24) * vp + s] = d.c;
         }
     } else {
         if (k > 0.0) {
@@ -296,6 +336,31 @@ __global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
 // ---------------------------------------------------------------------------
 // initialisation: cold (unit) or Haar-random links, times the background
 // ---------------------------------------------------------------------------
+// RANLUX state of one site during initialisation: every link's draws begin
+// a new block (the values are taken in order, so registers suffice).
+struct ranlux_init {
+    uint32_t b[24];
+    uint32_t c;
+    bool first;
+    LAT_DEV void load(const uint32_t* st, int64_t vp, int p, int64_t s) {
+#pragma unroll
+        for (int j = 0; j < 24; ++j) b[j] = st[((int64_t)p * 25 + j) * vp + s];
+        const uint32_t f = st[((int64_t)p * 25 + 24) * vp + s];
+        c = f & 1u;
+        first = (f & 2u) != 0;
+    }
+    LAT_DEV void draw(double* u, int n) {
+        ranlux_next_block(b, c, !first);
+        first = false;
+        for (int k = 0; k < n; ++k) u[k] = u24(b[k] << 8);
+    }
+    LAT_DEV void store(uint32_t* st, int64_t vp, int p, int64_t s) const {
+#pragma unroll
+        for (int j = 0; j < 24; ++j) st[((int64_t)p * 25 + j) * vp + s] = b[j];
+        st[((int64_t)p * 25 + 24) * vp + s] = c | (first ? 2u : 0u);
+    }
+};
+
 LAT_DEV void box_muller(double u1, double u2, double& g1, double& g2) {
     const double r = sqrt(-2.0 * log(u1));
     double sn, cs;
@@ -330,14 +395,17 @@ __global__ void __launch_bounds__(256) su3_init(InitArgs a) {
     const coord4 c = decode(a.g, s, p);
     const int64_t canon = canon_index(a.g, c);
     mrg_state st;
+    ranlux_init rl;
     if constexpr (RNG == LAT_RNG_MRG_I) {
         for (int w = 0; w < 6; ++w) st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
     }
+    if constexpr (RNG == LAT_RNG_RANLUX_I) rl.load(a.mrg, vp, p, s);
     for (int mu = 0; mu < 4; ++mu) {
         m3<double> U = identity3<double>();
         if (a.start == 1) {
             double u[12];
-            init_uniforms<RNG>(a, canon, mu, 12, u, st);
+            if constexpr (RNG == LAT_RNG_RANLUX_I) rl.draw(u, 12);
+            else init_uniforms<RNG>(a, canon, mu, 12, u, st);
 #pragma unroll
             for (int row = 0; row < 2; ++row)
 #pragma unroll
@@ -364,6 +432,9 @@ __global__ void __launch_bounds__(256) su3_init(InitArgs a) {
     if constexpr (RNG == LAT_RNG_MRG_I) {
         for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = st.s[w];
     }
+    if constexpr (RNG == LAT_RNG_RANLUX_I) {
+        if (a.start == 1) rl.store(a.mrg, vp, p, s);
+    }
 }
 
 template <class ST, int RNG>
@@ -375,14 +446,17 @@ __global__ void __launch_bounds__(256) su2_init(InitArgs a) {
     const coord4 c = decode(a.g, s, p);
     const int64_t canon = canon_index(a.g, c);
     mrg_state st;
+    ranlux_init rl;
     if constexpr (RNG == LAT_RNG_MRG_I) {
         for (int w = 0; w < 6; ++w) st.s[w] = a.mrg[((int64_t)p * 6 + w) * vp + s];
     }
+    if constexpr (RNG == LAT_RNG_RANLUX_I) rl.load(a.mrg, vp, p, s);
     for (int mu = 0; mu < 4; ++mu) {
         qt<double> U = {1.0, 0.0, 0.0, 0.0};
         if (a.start == 1) {
             double u[4], g[4];
-            init_uniforms<RNG>(a, canon, mu, 4, u, st);
+            if constexpr (RNG == LAT_RNG_RANLUX_I) rl.draw(u, 4);
+            else init_uniforms<RNG>(a, canon, mu, 4, u, st);
             box_muller(u[0], u[1], g[0], g[1]);
             box_muller(u[2], u[3], g[2], g[3]);
             const double nn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3]);
@@ -400,6 +474,9 @@ __global__ void __launch_bounds__(256) su2_init(InitArgs a) {
     }
     if constexpr (RNG == LAT_RNG_MRG_I) {
         for (int w = 0; w < 6; ++w) a.mrg[((int64_t)p * 6 + w) * vp + s] = st.s[w];
+    }
+    if constexpr (RNG == LAT_RNG_RANLUX_I) {
+        if (a.start == 1) rl.store(a.mrg, vp, p, s);
     }
 }
 
@@ -880,6 +957,9 @@ hipError_t pass_dispatch(int kind, bool reunit, int rng, const PassArgs& a, int 
         case LAT_RNG_PHILOX_I:
             return reunit ? launch_one<ST, SU3, 0, true, LAT_RNG_PHILOX_I>(a, block, st)
                           : launch_one<ST, SU3, 0, false, LAT_RNG_PHILOX_I>(a, block, st);
+        case LAT_RNG_RANLUX_I:
+            return reunit ? launch_one<ST, SU3, 0, true, LAT_RNG_RANLUX_I>(a, block, st)
+                          : launch_one<ST, SU3, 0, false, LAT_RNG_RANLUX_I>(a, block, st);
         default:
             return reunit ? launch_one<ST, SU3, 0, true, LAT_RNG_CONST_I>(a, block, st)
                           : launch_one<ST, SU3, 0, false, LAT_RNG_CONST_I>(a, block, st);
@@ -913,6 +993,10 @@ static hipError_t init_dispatch(int rng, const InitArgs& a, hipStream_t st) {
         case LAT_RNG_PHILOX_I:
             if constexpr (SU3) hipLaunchKernelGGL((su3_init<ST, LAT_RNG_PHILOX_I>), grid, dim3(256), 0, st, a);
             else hipLaunchKernelGGL((su2_init<ST, LAT_RNG_PHILOX_I>), grid, dim3(256), 0, st, a);
+            break;
+        case LAT_RNG_RANLUX_I:
+            if constexpr (SU3) hipLaunchKernelGGL((su3_init<ST, LAT_RNG_RANLUX_I>), grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((su2_init<ST, LAT_RNG_RANLUX_I>), grid, dim3(256), 0, st, a);
             break;
         default:
             if constexpr (SU3) hipLaunchKernelGGL((su3_init<ST, LAT_RNG_CONST_I>), grid, dim3(256), 0, st, a);

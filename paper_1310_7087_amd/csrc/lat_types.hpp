@@ -5,6 +5,7 @@
 #define LAT_RNG_MRG_I 0
 #define LAT_RNG_PHILOX_I 1
 #define LAT_RNG_CONST_I 2
+#define LAT_RNG_RANLUX_I 3
 
 #define LAT_ST_F64 0
 #define LAT_ST_F32 1

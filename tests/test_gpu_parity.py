@@ -523,3 +523,62 @@ def test_frozen_flag_survives_a_checkpoint(tmp_path):
     a.sweep(1, 2)
     b.sweep(1, 2)
     assert np.array_equal(a.get_links(), b.get_links())
+
+
+def swb_blocks(seed: int, n_blocks: int):
+    """RANLUX luxury 3 written out: the Lehmer-seeded subtract-with-borrow
+    generator, every 223rd group of outputs cut to its first 24; returns the
+    delivered blocks and the carry after each."""
+    e = seed
+    x = []
+    for _ in range(24):
+        e = (40014 * e) % 2147483563
+        x.append(e % (1 << 24))
+    c = 1 if x[-1] == 0 else 0
+    blocks, carries = [], []
+    for b in range(n_blocks):
+        out = []
+        for k in range(223 if b else 24):
+            y = x[-10] - x[-24] - c
+            c = 1 if y < 0 else 0
+            y %= 1 << 24
+            x = x[1:] + [y]
+            out.append(y)
+        blocks.append(out[-24:] if b else out)
+        carries.append(c)
+    return blocks, carries
+
+
+@pytest.mark.parametrize("group,dims,beta", [(3, (8, 6, 4, 4), 5.7), (2, (6, 6, 4, 4), 2.3)])
+def test_ranlux_streams(group, dims, beta):
+    """RANLUX luxury 3 per-site streams against the oracle: the hot start,
+    three heat-bath sweeps (every accept decision) and a compound sweep from
+    cold; the stored state of sample sites against the generator written
+    out (four delivered blocks after the hot start, one per link)."""
+    g, o = pair(group, dims, beta, rng=O.RNG_RANLUX, seed=77, start=O.HOT)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    st = g.rng_state()
+    for i in (0, 1, 37, int(np.prod(dims)) - 1):
+        blocks, carries = swb_blocks(O.ranlux_site_seed(77, i, 0), 4)
+        assert list(st[i, :24]) == blocks[3] and st[i, 24] == carries[3], i
+    g.set_accept_log(True)
+    o.enable_accept_log(True)
+    for _ in range(3):
+        g.sweep(1, 0)
+        o.sweep(1, 0)
+        assert np.array_equal(g.accept_log(), o.accept_log())
+        assert maxdiff(g.get_links(), o.get_links()) < TOL64
+    g, o = pair(group, dims, beta, rng=O.RNG_RANLUX, seed=78, start=O.COLD)
+    g.sweep(1, 4)
+    o.sweep(1, 4)
+    assert maxdiff(g.get_links(), o.get_links()) < TOL64
+
+
+def test_ranlux_state_survives_a_checkpoint(tmp_path):
+    a = P.Lattice(3, (8, 6, 4, 4), 5.7, 0, rng=P.RNG_RANLUX, seed=5, start=P.HOT)
+    a.sweep(1, 2)
+    a.save(str(tmp_path / "r.ckpt"))
+    b = P.load_lattice(str(tmp_path / "r.ckpt"), 3, (8, 6, 4, 4))
+    a.sweep(2, 2)
+    b.sweep(2, 2)
+    assert np.array_equal(a.get_links(), b.get_links())
