@@ -77,6 +77,17 @@ def lib():
         L.orc_ranlux_standard_values.argtypes = [vp]
         L.orc_ranlux_site_seed.argtypes = [u64, i64, u32]
         L.orc_ranlux_site_seed.restype = u32
+        L.orc_on_create.restype = vp
+        L.orc_on_create.argtypes = [i, i, i, i, i, d, d, d, d, i, d, u64, i, u32, i]
+        L.orc_on_destroy.argtypes = [vp]
+        L.orc_on_sweep.argtypes = [vp, i]
+        L.orc_on_measure.argtypes = [vp, vp]
+        L.orc_on_get_field.argtypes = [vp, vp]
+        L.orc_on_set_field.argtypes = [vp, vp]
+        L.orc_on_sweeps.argtypes = [vp]
+        L.orc_on_sweeps.restype = u64
+        L.orc_on_acceptance.argtypes = [vp]
+        L.orc_on_acceptance.restype = d
         _lib = L
     return _lib
 
@@ -230,3 +241,50 @@ def update_link(group, beta, nhit, kind, reunit, U, A, u):
     used = lib().orc_update_link(n, float(beta), int(nhit), int(kind), int(reunit),
                                  _ptr(Uc), _ptr(Ar), _ptr(uu), _ptr(out))
     return out, used
+
+
+class ONField:
+    """O(N) phi^4 model in the oracle: an N-vector per site (N = 1..4),
+    multi-hit Metropolis with NHIT hits per site and sweep.  The field is
+    exchanged as FP64 ``[site][component]``.  ``measure()`` returns
+    (<phi^2>, <phi(x).phi(x+mu)>, <(phi^2-1)^2>, <phi_0>, .., <phi_3>)."""
+
+    def __init__(self, ncomp, dims, kappa, lam, h=0.0, delta=1.0, rng=RNG_PHILOX, rng_const=0.5,
+                 seed=1, nhit=100, lattice_id=0, start=HOT):
+        self.n = int(ncomp)
+        self.dims = tuple(int(x) for x in dims)
+        self.V = int(np.prod(self.dims))
+        h_ = lib().orc_on_create(self.n, *self.dims, float(kappa), float(lam), float(h), float(delta),
+                                 int(rng), float(rng_const), int(seed), int(nhit), int(lattice_id), int(start))
+        if not h_:
+            raise ValueError("oracle rejected the O(N) parameters")
+        self._h = h_
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_on_destroy(h)
+            self._h = None
+
+    def sweep(self, n=1):
+        lib().orc_on_sweep(self._h, int(n))
+
+    def measure(self) -> np.ndarray:
+        out = np.zeros(7)
+        lib().orc_on_measure(self._h, _ptr(out))
+        return out
+
+    def get_field(self) -> np.ndarray:
+        out = np.empty((self.V, self.n))
+        lib().orc_on_get_field(self._h, _ptr(out))
+        return out
+
+    def set_field(self, phi: np.ndarray) -> None:
+        a = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.V, self.n)
+        lib().orc_on_set_field(self._h, _ptr(a))
+
+    def sweeps(self) -> int:
+        return int(lib().orc_on_sweeps(self._h))
+
+    def acceptance(self) -> float:
+        return float(lib().orc_on_acceptance(self._h))

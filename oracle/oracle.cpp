@@ -882,3 +882,211 @@ int orc_update_link(int group, double beta, int nhit, int kind, int reunit, cons
     to_canonical(n, R, Uout);
     return d.pos;
 }
+
+/* ================================================================== */
+/* O(N) lambda phi^4 model (the paper's second model family, Sec. 3.3  */
+/* and Sec. 5): an N-vector phi(x) per site, N = 1..4.                 */
+/* ================================================================== */
+/*
+ * Action (a reading: the paper names the model and its coupling only; this
+ * is the standard hopping-parameter form of the lattice O(N) phi^4 theory,
+ * plus a constant source h along component 0 for the external field):
+ *   S = sum_x [ -2 kappa sum_{mu} phi(x).phi(x+mu) + phi(x)^2
+ *               + lambda (phi(x)^2 - 1)^2 - h phi_0(x) ].
+ * Local action of one site with neighbour sum F = sum_mu [phi(x+mu) + phi(x-mu)]:
+ *   s(phi) = -2 kappa F.phi + phi.phi + lambda (phi.phi - 1)^2 - h phi_0.
+ * Update ("improved" multi-hit Metropolis, Sec. 3.3; NHIT hits per site,
+ * Sec. 5): checkerboard, parity 0 sites then parity 1; at each site NHIT
+ * successive Metropolis steps with the neighbours fixed: proposal
+ * phi' = phi + delta r, r_a = 2 u_a - 1, accepted iff u_acc < exp(-(s(phi') - s(phi))).
+ * Draws of hit k of sweep number w at site i:
+ *   Philox: counter (i, lattice_id, w, k) -> words w0..w3; u_a from word a
+ *           (a < N); u_acc from the 24-bit word formed by the low bytes of
+ *           w0, w1, w2 (high to low);
+ *   RANLUX: every site update begins a new block; per hit N values for r
+ *           then one for u_acc;
+ *   constant: every uniform = c.
+ * Starts: cold phi = (1, 0, ..., 0); hot phi_a = 2 u_a - 1 with Philox counter
+ * (i, lattice_id, 0, 0xFFFFFFFF), or the first N values of a RANLUX block.
+ */
+struct orc_on {
+    int n;
+    int d[4];
+    int64_t V;
+    double kappa, lambda, h, delta;
+    int rng;
+    double rng_const;
+    uint64_t seed;
+    int nhit;
+    uint32_t lat_id;
+    uint64_t sweeps;
+    int64_t accepted_last;  // accepted hits of the most recent sweep
+    std::vector<double> phi;        // [i][n]
+    std::vector<RanluxSite> ranlux;  // one stream per site
+};
+
+static void on_coords(const orc_on* L, int64_t i, int x[4]) {
+    for (int m = 0; m < 4; ++m) {
+        x[m] = (int)(i % L->d[m]);
+        i /= L->d[m];
+    }
+}
+static int64_t on_index(const orc_on* L, const int x[4]) {
+    return x[0] + (int64_t)L->d[0] * (x[1] + (int64_t)L->d[1] * (x[2] + (int64_t)L->d[2] * x[3]));
+}
+static int64_t on_shift(const orc_on* L, int64_t i, int mu, int step) {
+    int x[4];
+    on_coords(L, i, x);
+    x[mu] = (x[mu] + step + L->d[mu]) % L->d[mu];
+    return on_index(L, x);
+}
+static double dot_n(int n, const double* a, const double* b) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += a[k] * b[k];
+    return s;
+}
+static double on_local_action(const orc_on* L, const double* F, const double* p) {
+    const double p2 = dot_n(L->n, p, p);
+    return -2.0 * L->kappa * dot_n(L->n, F, p) + p2 + L->lambda * (p2 - 1.0) * (p2 - 1.0) - L->h * p[0];
+}
+static double accept_word(uint32_t w0, uint32_t w1, uint32_t w2) {
+    return orc_uniform24(((w0 & 0xFFu) << 24) | ((w1 & 0xFFu) << 16) | ((w2 & 0xFFu) << 8));
+}
+
+orc_on* orc_on_create(int ncomp, int nx, int ny, int nz, int nt, double kappa, double lambda, double h,
+                      double delta, int rng, double rng_const, uint64_t seed, int nhit, uint32_t lattice_id,
+                      int start) {
+    int dims[4] = {nx, ny, nz, nt};
+    if (ncomp < 1 || ncomp > 4) return nullptr;
+    for (int m = 0; m < 4; ++m)
+        if (dims[m] < 2 || dims[m] % 2) return nullptr;
+    if (!std::isfinite(kappa) || !(lambda >= 0.0) || !std::isfinite(lambda) || !std::isfinite(h) ||
+        !(delta > 0.0) || !std::isfinite(delta))
+        return nullptr;
+    if (nhit < 1 || nhit > 1000) return nullptr;
+    if (rng != ORC_RNG_PHILOX && rng != ORC_RNG_CONST && rng != ORC_RNG_RANLUX) return nullptr;
+    orc_on* L = new orc_on();
+    L->n = ncomp;
+    for (int m = 0; m < 4; ++m) L->d[m] = dims[m];
+    L->V = (int64_t)nx * ny * nz * nt;
+    L->kappa = kappa;
+    L->lambda = lambda;
+    L->h = h;
+    L->delta = delta;
+    L->rng = rng;
+    L->rng_const = rng_const;
+    L->seed = seed;
+    L->nhit = nhit;
+    L->lat_id = lattice_id;
+    L->sweeps = 0;
+    L->accepted_last = 0;
+    L->phi.assign(L->V * ncomp, 0.0);
+    if (rng == ORC_RNG_RANLUX) {
+        L->ranlux.resize(L->V);
+        for (int64_t i = 0; i < L->V; ++i) L->ranlux[i].eng.seed(ranlux_site_seed(seed, i, lattice_id));
+    }
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < L->V; ++i) {
+        double* p = &L->phi[i * ncomp];
+        if (start == ORC_COLD) {
+            p[0] = 1.0;
+            continue;
+        }
+        double u[4];
+        if (rng == ORC_RNG_PHILOX) {
+            uint32_t c[4] = {(uint32_t)i, lattice_id, 0u, 0xFFFFFFFFu}, o[4];
+            orc_philox4x32_10(c, key, o);
+            for (int a = 0; a < 4; ++a) u[a] = orc_uniform24(o[a]);
+        } else if (rng == ORC_RNG_RANLUX) {
+            L->ranlux[i].begin_update();
+            for (int a = 0; a < ncomp; ++a) u[a] = L->ranlux[i].next();
+        } else {
+            for (int a = 0; a < 4; ++a) u[a] = rng_const;
+        }
+        for (int a = 0; a < ncomp; ++a) p[a] = 2.0 * u[a] - 1.0;
+    }
+    return L;
+}
+
+void orc_on_destroy(orc_on* L) { delete L; }
+
+/* One sweep: every site of parity 0, then every site of parity 1. */
+void orc_on_sweep(orc_on* L, int nsweeps) {
+    const int n = L->n;
+    const uint32_t key[2] = {(uint32_t)L->seed, (uint32_t)(L->seed >> 32)};
+    for (int w = 0; w < nsweeps; ++w) {
+        int64_t acc_total = 0;
+        for (int p = 0; p < 2; ++p) {
+#pragma omp parallel for schedule(static) reduction(+ : acc_total)
+            for (int64_t i = 0; i < L->V; ++i) {
+                int x[4];
+                on_coords(L, i, x);
+                if ((x[0] + x[1] + x[2] + x[3]) % 2 != p) continue;
+                double F[4] = {0, 0, 0, 0};
+                for (int mu = 0; mu < 4; ++mu) {
+                    const double* fw = &L->phi[on_shift(L, i, mu, +1) * n];
+                    const double* bw = &L->phi[on_shift(L, i, mu, -1) * n];
+                    for (int a = 0; a < n; ++a) F[a] += fw[a] + bw[a];
+                }
+                double* ph = &L->phi[i * n];
+                if (L->rng == ORC_RNG_RANLUX) L->ranlux[i].begin_update();
+                for (int k = 0; k < L->nhit; ++k) {
+                    double u[4], uacc;
+                    if (L->rng == ORC_RNG_PHILOX) {
+                        uint32_t c[4] = {(uint32_t)i, L->lat_id, (uint32_t)L->sweeps, (uint32_t)k}, o[4];
+                        orc_philox4x32_10(c, key, o);
+                        for (int a = 0; a < 4; ++a) u[a] = orc_uniform24(o[a]);
+                        uacc = accept_word(o[0], o[1], o[2]);
+                    } else if (L->rng == ORC_RNG_RANLUX) {
+                        for (int a = 0; a < n; ++a) u[a] = L->ranlux[i].next();
+                        uacc = L->ranlux[i].next();
+                    } else {
+                        for (int a = 0; a < 4; ++a) u[a] = L->rng_const;
+                        uacc = L->rng_const;
+                    }
+                    double trial[4];
+                    for (int a = 0; a < n; ++a) trial[a] = ph[a] + L->delta * (2.0 * u[a] - 1.0);
+                    const double dS = on_local_action(L, F, trial) - on_local_action(L, F, ph);
+                    if (uacc < std::exp(-dS)) {
+                        for (int a = 0; a < n; ++a) ph[a] = trial[a];
+                        ++acc_total;
+                    }
+                }
+            }
+        }
+        L->accepted_last = acc_total;
+        L->sweeps += 1;
+    }
+}
+
+/* out = { <phi^2>, <phi(x).phi(x+mu)> over sites and the 4 directions,
+ *         <(phi^2 - 1)^2>, <phi_0>, <phi_1>, <phi_2>, <phi_3> } (components
+ * beyond N are 0).  Compensated sums in site order. */
+void orc_on_measure(const orc_on* L, double out[7]) {
+    const int n = L->n;
+    std::vector<double> p2(L->V), lk(L->V), q(L->V), m[4];
+    for (int a = 0; a < 4; ++a) m[a].assign(L->V, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < L->V; ++i) {
+        const double* ph = &L->phi[i * n];
+        const double s2 = dot_n(n, ph, ph);
+        p2[i] = s2;
+        q[i] = (s2 - 1.0) * (s2 - 1.0);
+        double l = 0.0;
+        for (int mu = 0; mu < 4; ++mu) l += dot_n(n, ph, &L->phi[on_shift(L, i, mu, +1) * n]);
+        lk[i] = l;
+        for (int a = 0; a < n; ++a) m[a][i] = ph[a];
+    }
+    const double V = (double)L->V;
+    out[0] = neumaier(p2) / V;
+    out[1] = neumaier(lk) / (4.0 * V);
+    out[2] = neumaier(q) / V;
+    for (int a = 0; a < 4; ++a) out[3 + a] = neumaier(m[a]) / V;
+}
+
+void orc_on_get_field(const orc_on* L, double* out) { std::memcpy(out, L->phi.data(), L->phi.size() * sizeof(double)); }
+void orc_on_set_field(orc_on* L, const double* in) { std::memcpy(L->phi.data(), in, L->phi.size() * sizeof(double)); }
+uint64_t orc_on_sweeps(const orc_on* L) { return L->sweeps; }
+double orc_on_acceptance(const orc_on* L) {
+    return (double)L->accepted_last / ((double)L->V * (double)L->nhit);
+}

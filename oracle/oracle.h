@@ -89,6 +89,23 @@ int  orc_update_link(int group, double beta, int nhit, int kind, int reunit,
 /* Staple of link (i, mu) in the W-frame as an N x N complex matrix. */
 void orc_staple(const orc_lattice* L, int64_t i, int mu, double* A);
 
+/* ---- O(N) phi^4 model: N-vector per site, multi-hit Metropolis ---- */
+typedef struct orc_on orc_on;
+/* ncomp = N in 1..4; rng Philox, constant or RANLUX; nhit 1..1000;
+ * lambda >= 0, delta > 0.  Returns NULL on invalid arguments.  Field layout
+ * [site i][component a], FP64. */
+orc_on* orc_on_create(int ncomp, int nx, int ny, int nz, int nt, double kappa, double lambda, double h,
+                      double delta, int rng, double rng_const, uint64_t seed, int nhit, uint32_t lattice_id,
+                      int start);
+void orc_on_destroy(orc_on* L);
+void orc_on_sweep(orc_on* L, int nsweeps);
+void orc_on_measure(const orc_on* L, double out[7]);
+void orc_on_get_field(const orc_on* L, double* out);
+void orc_on_set_field(orc_on* L, const double* in);
+uint64_t orc_on_sweeps(const orc_on* L);
+/* Accepted hits of the most recent sweep / (V * NHIT). */
+double orc_on_acceptance(const orc_on* L);
+
 #ifdef __cplusplus
 }
 #endif
