@@ -15,8 +15,8 @@ Also reported: the FP32, 12-real FP32 and 12-real FP64 storage forms
 roofline of the dominant pass kernel (event-timed in this run), SU(3)
 64^3 x 16 (the case that does not fit the last-level cache), the 64-lattice
 batch in FP32 against the same lattices run one by one in FP64, the paper's
-own Table 1 working sweeps (SU(3) 32^4, SU(2) 44^4; its 2011 figures as
-context), and the FP64 CPU oracle timed on a bounded sample of the headline
+own Table 1 working sweeps (SU(3) 32^4, SU(2) 44^4, and the O(4) model on
+16^4 .. 72^4; its 2011 figures as context), and the FP64 CPU oracle timed on a bounded sample of the headline
 workload on the host cores.
 Prints one JSON line.
 """
@@ -336,6 +336,87 @@ def run_paper_workloads(P, sweeps: int = 20):
     return out
 
 
+# O(4) phi^4 model, the paper's other Table 1 workload: lattice, the
+# paper's NHIT = 100 Metropolis hits per site, and a benchmark point in the
+# model's coupling space (the paper gives none; delta gives about the 50%
+# acceptance the paper mentions).
+O4_KAPPA, O4_LAMBDA, O4_DELTA, O4_NHIT = 0.3, 1.0, 0.55, 100
+# Seconds per working sweep of its fastest single-device run per lattice (SP, DP).
+PAPER_TABLE1_O4 = [
+    {"L": 16, "paper": {"device": "GeForce GTX 560M", "f32": 0.08, "f64": 0.12}},
+    {"L": 24, "paper": {"device": "GeForce GTX 560M", "f32": 0.42, "f64": 0.6}},
+    {"L": 32, "paper": {"device": "Radeon HD 7970 (2 parts)", "f32": 0.66, "f64": 0.95}},
+    {"L": 48, "paper": {"device": "GeForce GTX 560 Ti (4 parts)", "f32": 4.64, "f64": 6.10}},
+    {"L": 72, "paper": {"device": "Radeon HD 7970 (12 parts)", "f32": 20.35, "f64": 36.2}},
+]
+O4_SOURCES = ["paper_1310_7087_amd/csrc/lat_on.hip", "paper_1310_7087_amd/csrc/lat_dev.hpp",
+              "paper_1310_7087_amd/csrc/lat_types.hpp"]
+# one wave64 VALU instruction per compute unit and cycle (4 SIMDs of 16
+# lanes, 4 cycles per wave64 instruction), 256 CUs at 2.4 GHz
+VALU_WAVE_INSTR_PEAK = 256 * 2.4e9
+
+
+def o4_valu_per_hit():
+    """VALU wave-instructions per Metropolis hit of the O(4) pass kernel from
+    the committed rocprofv3 counters, if the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "pmc_o4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    h = hashlib.sha256()
+    for f in O4_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if data.get("kernel_hash") != h.hexdigest()[:16]:
+        return None
+    return data.get("valu_wave_instructions_per_hit")
+
+
+def run_o4(P, sweeps: int = 10, sizes=None):
+    """The paper's Table 1 O(4) lattices: working sweeps (sweep + measurement)
+    with RANLUX (the paper's generator) and Philox, FP64 and FP32 storage."""
+    out = []
+    for w in PAPER_TABLE1_O4:
+        if sizes and w["L"] not in sizes:
+            continue
+        dims = (w["L"],) * 4
+        V = volume(dims)
+        row = {"lattice": list(dims), "kappa": O4_KAPPA, "lambda": O4_LAMBDA, "delta": O4_DELTA, "nhit": O4_NHIT,
+               "paper_seconds_per_working_sweep": w["paper"]}
+        for form, st in (("f64", P.F64), ("f32", P.F32)):
+            for gen, rng in (("ranlux", P.RNG_RANLUX), ("philox", P.RNG_PHILOX)):
+                f = P.ONField(4, dims, O4_KAPPA, O4_LAMBDA, 0.0, O4_DELTA, storage=st, rng=rng, seed=5,
+                              nhit=O4_NHIT)
+                f.run(2, 1)
+                t0 = time.perf_counter()
+                f.run(sweeps, 1)
+                dt = (time.perf_counter() - t0) / sweeps
+                row[f"{form}_{gen}"] = {"seconds_per_working_sweep": dt, "site_updates_per_s": V / dt,
+                                        "hits_per_s": V * O4_NHIT / dt, "acceptance": f.acceptance(),
+                                        "speedup_vs_paper": w["paper"][form] / dt}
+                f.close()
+        log(f"[O(4) {w['L']}^4] F64 RANLUX {row['f64_ranlux']['seconds_per_working_sweep'] * 1e3:.2f} ms, "
+            f"Philox {row['f64_philox']['seconds_per_working_sweep'] * 1e3:.2f} ms per working sweep")
+        out.append(row)
+    # the pass kernel's VALU issue rate at 32^4 (FP64, Philox)
+    f = P.ONField(4, (32,) * 4, O4_KAPPA, O4_LAMBDA, 0.0, O4_DELTA, storage=P.F64, rng=P.RNG_PHILOX, seed=5,
+                  nhit=O4_NHIT)
+    f.sweep(2)
+    ms = f.profile(20)
+    f.close()
+    hits = volume((32,) * 4) // 2 * O4_NHIT
+    per_hit = o4_valu_per_hit()
+    roof = {"bound": "alu", "kernel": "on_pass<f64, N=4, philox>", "avg_launch_us": ms * 1e3,
+            "hits_per_launch": hits, "hits_per_s": hits / (ms * 1e-3), "unit": "VALU wave-instructions/s",
+            "peak": VALU_WAVE_INSTR_PEAK, "valu_wave_instructions_per_hit": per_hit,
+            "achieved": None, "frac": None}
+    if per_hit:
+        roof["achieved"] = hits * per_hit / (ms * 1e-3)
+        roof["frac"] = roof["achieved"] / VALU_WAVE_INSTR_PEAK
+    return {"table1": out, "o4_32_pass_roofline": roof}
+
+
 def cpu_baseline(steps: int):
     import oracle as O
     cores = len(os.sched_getaffinity(0))
@@ -400,6 +481,9 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size kernel that "
                          "calibrates the profiler's HBM byte counters)")
+    ap.add_argument("--o4-only", action="store_true",
+                    help="only run the O(4) model's Table 1 lattices and print their JSON line")
+    ap.add_argument("--o4-sizes", default="16,24,32,48,72", help="O(4) lattice extents L (L^4) to run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice is resident on a single MI355X); "
@@ -414,6 +498,11 @@ def main() -> int:
     if args.precision_study > 0:
         print(json.dumps({"precision_study": precision_study(P, args.precision_study),
                           "workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or"}), flush=True)
+        return 0
+
+    if args.o4_only:
+        sizes = {int(x) for x in args.o4_sizes.split(",") if x.strip()}
+        print(json.dumps({"o4_paper_table1": run_o4(P, sizes=sizes)}), flush=True)
         return 0
 
     if args.copy_mib > 0:
@@ -484,6 +573,7 @@ def main() -> int:
         out["su3_64x16"] = run_large(P)
         out["batch_64_lattices"] = run_batch(P, precision_sweeps=args.precision_sweeps)
         out["paper_table1_workloads"] = run_paper_workloads(P)
+        out["o4_paper_table1"] = run_o4(P)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)

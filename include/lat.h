@@ -285,6 +285,88 @@ int lat_batch_get_links(lat_batch_t b, int i, double* host, size_t n_doubles);
 int lat_batch_set_links(lat_batch_t b, int i, const double* host, size_t n_doubles);
 int lat_batch_destroy(lat_batch_t b);
 
+/* ------------------------------------------------------------------ */
+/* O(N) models (the paper's second model family, Sec. 3.3 and 5): an   */
+/* N-vector field phi(x) on the sites, N = 1..4, with the lattice       */
+/* phi^4 action in hopping-parameter form and a constant source h      */
+/* along component 0 (the external field):                             */
+/*   S = sum_x [ -2 kappa sum_mu phi(x).phi(x+mu) + phi(x)^2            */
+/*               + lambda (phi(x)^2 - 1)^2 - h phi_0(x) ].              */
+/* The paper names the model, its coupling-constant dependence (Sec. 1) */
+/* and an improved Metropolis update with NHIT = 100 tries per site     */
+/* (Sec. 3.3, Sec. 5) but writes out neither; this form is the reading. */
+/* ------------------------------------------------------------------ */
+typedef struct lat_on_ctx* lat_on_t;
+
+/* Device bytes of an O(N) field with these parameters (0 if invalid). */
+size_t lat_on_device_bytes(int ncomp, int Nx, int Ny, int Nz, int Nt, const lat_options* opt);
+
+/*
+ * Creates an O(N) field on the current HIP device and initialises it: cold
+ * phi = (1, 0, ..), hot phi_a = 2 u_a - 1 (uniform in the cube [-1, 1]^N).
+ *   ncomp: N in 1..4; kappa: hopping parameter (finite); lambda >= 0;
+ *   h: source along component 0; delta > 0: proposal half-width.
+ *   opt: storage LAT_F64 or LAT_F32 (field storage; all update and
+ *   reduction arithmetic is FP64 in both), rng LAT_RNG_PHILOX,
+ *   LAT_RNG_RANLUX or LAT_RNG_CONST (others LAT_EUNSUPPORTED), nhit = hits
+ *   per site and sweep 1..1000 (NULL opt: 100, the paper's value), seed,
+ *   lattice_id, start, stream, device_buffer/device_bytes and block_size as
+ *   for lat_create; frozen must be LAT_FROZEN_NONE; the tile, layout and
+ *   occupancy fields are ignored.
+ * Draws: Philox counter (canonical site, lattice_id, sweep number, hit k)
+ * gives one 4-word block per hit: u_a from the high 24 bits of word a
+ * (a < N), the acceptance uniform from the low bytes of words 0, 1, 2; the
+ * hot start uses counter (site, lattice_id, 0, 0xFFFFFFFF).  RANLUX (seeded
+ * as for lat_create): every site update begins a new block, each hit takes
+ * N values then the acceptance value; the hot start takes the first N values
+ * of the first block.
+ */
+int lat_on_create(lat_on_t* out, int ncomp, int Nx, int Ny, int Nz, int Nt, double kappa, double lambda,
+                  double h, double delta, const lat_options* opt);
+
+/*
+ * n_sweeps sweeps (asynchronous).  A sweep updates every site of parity 0,
+ * then every site of parity 1 (the neighbours of a site have the other
+ * parity); each site gets NHIT successive Metropolis hits with its
+ * neighbours fixed: phi' = phi + delta (2u - 1), accepted iff
+ * u_acc < exp(-(s(phi') - s(phi))) with the local action
+ * s(phi) = -2 kappa F.phi + phi.phi + lambda (phi.phi - 1)^2 - h phi_0,
+ * F = sum_mu [phi(x+mu) + phi(x-mu)].
+ */
+int lat_on_sweep(lat_on_t h, int n_sweeps);
+
+/*
+ * Measures (synchronously) obs = { <phi^2>, <phi(x).phi(x+mu)> averaged
+ * over sites and the 4 directions, <(phi^2 - 1)^2>, <phi_0>, <phi_1>,
+ * <phi_2>, <phi_3> } (components beyond N are 0).  FP64 sums in a fixed
+ * order with a compensated final reduction.  The action per site is
+ * -8 kappa obs[1] + obs[0] + lambda obs[2] - h obs[3].
+ */
+int lat_on_measure(lat_on_t h, double obs[7]);
+
+/* n_sweeps sweeps with a measurement after every measure_every-th (0 =
+ * none) into series[k][7] (may be NULL), k = n_sweeps / measure_every;
+ * synchronises at the end. */
+int lat_on_run(lat_on_t h, int n_sweeps, int measure_every, double* series);
+
+/* Accepted hits of the most recent sweep / (V * NHIT); synchronises.
+ * LAT_ESTATE before the first sweep. */
+int lat_on_acceptance(lat_on_t h, double* rate);
+
+/* Field as FP64 [site i][component a], i canonical; n_doubles = V * N.
+ * set rounds to the storage form.  Both synchronise. */
+int lat_on_get_field(lat_on_t h, double* host, size_t n_doubles);
+int lat_on_set_field(lat_on_t h, const double* host, size_t n_doubles);
+int lat_on_get_info(lat_on_t h, uint64_t* seed_used, uint64_t* sweeps_done);
+
+/* Runs `reps` sweeps launched back to back between two HIP events on the
+ * handle's stream and returns the average duration of one pass (half a
+ * sweep) in milliseconds.  The field advances as with lat_on_sweep. */
+int lat_on_profile(lat_on_t h, int reps, double* ms_per_pass);
+
+/* Releases the handle; NULL is a no-op. */
+int lat_on_destroy(lat_on_t h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,21 @@ def _load():
     L.lat_batch_get_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_set_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_destroy.argtypes = [vp]
+    L.lat_on_device_bytes.argtypes = [i, i, i, i, i, P(Options)]
+    L.lat_on_device_bytes.restype = sz
+    L.lat_on_create.argtypes = [P(vp), i, i, i, i, i, d, d, d, d, P(Options)]
+    L.lat_on_sweep.argtypes = [vp, i]
+    L.lat_on_measure.argtypes = [vp, vp]
+    L.lat_on_run.argtypes = [vp, i, i, vp]
+    L.lat_on_acceptance.argtypes = [vp, P(d)]
+    L.lat_on_get_field.argtypes = [vp, vp, sz]
+    L.lat_on_set_field.argtypes = [vp, vp, sz]
+    L.lat_on_get_info.argtypes = [vp, P(u64), P(u64)]
+    L.lat_on_profile.argtypes = [vp, i, P(d)]
+    L.lat_on_destroy.argtypes = [vp]
+    for name in ("lat_on_create", "lat_on_sweep", "lat_on_measure", "lat_on_run", "lat_on_acceptance",
+                 "lat_on_get_field", "lat_on_set_field", "lat_on_get_info", "lat_on_profile", "lat_on_destroy"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_set_links",
                  "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_autotune", "lat_set_accept_log", "lat_save", "lat_load",
                  "lat_destroy", "lat_philox4x32_10", "lat_batch_create", "lat_batch_run",
@@ -336,3 +351,73 @@ class Batch:
     def set_links(self, i, links) -> None:
         a = np.ascontiguousarray(links, dtype=np.float64)
         _check(lib.lat_batch_set_links(self._h, int(i), _ptr(a), a.size))
+
+
+def on_device_bytes(ncomp, dims, **kw) -> int:
+    kw.setdefault("nhit", 100)
+    o = make_options(**kw)
+    return int(lib.lat_on_device_bytes(int(ncomp), *[int(x) for x in dims], ctypes.byref(o)))
+
+
+class ONField:
+    """An O(N) phi^4 field (N = 1..4) on the GPU: ``lat_on_*`` of the C ABI.
+    The field is exchanged as FP64 ``[site][component]``; ``measure()``
+    returns (<phi^2>, <phi(x).phi(x+mu)>, <(phi^2-1)^2>, <phi_0>, .., <phi_3>)."""
+
+    def __init__(self, ncomp, dims, kappa, lam, h=0.0, delta=1.0, storage=F64, rng=RNG_PHILOX,
+                 rng_const=0.5, seed=1, nhit=100, lattice_id=0, start=HOT, stream=None, block_size=0):
+        self.n = int(ncomp)
+        self.dims = tuple(int(x) for x in dims)
+        self.V = int(np.prod(self.dims))
+        o = make_options(storage=storage, rng=rng, rng_const=rng_const, start=start, seed=seed, nhit=nhit,
+                         lattice_id=lattice_id, stream=stream, block_size=block_size)
+        h_ = ctypes.c_void_p()
+        _check(lib.lat_on_create(ctypes.byref(h_), self.n, *self.dims, float(kappa), float(lam), float(h),
+                                 float(delta), ctypes.byref(o)))
+        self._h = h_
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.lat_on_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def sweep(self, n=1):
+        _check(lib.lat_on_sweep(self._h, int(n)))
+
+    def measure(self) -> np.ndarray:
+        out = np.zeros(7)
+        _check(lib.lat_on_measure(self._h, _ptr(out)))
+        return out
+
+    def run(self, n_sweeps, measure_every=1) -> np.ndarray:
+        k = n_sweeps // measure_every if measure_every else 0
+        out = np.zeros((max(k, 1), 7))
+        _check(lib.lat_on_run(self._h, int(n_sweeps), int(measure_every), _ptr(out)))
+        return out[:k]
+
+    def acceptance(self) -> float:
+        r = ctypes.c_double()
+        _check(lib.lat_on_acceptance(self._h, ctypes.byref(r)))
+        return r.value
+
+    def get_field(self) -> np.ndarray:
+        out = np.empty((self.V, self.n))
+        _check(lib.lat_on_get_field(self._h, _ptr(out), out.size))
+        return out
+
+    def set_field(self, phi) -> None:
+        a = np.ascontiguousarray(phi, dtype=np.float64).reshape(self.V, self.n)
+        _check(lib.lat_on_set_field(self._h, _ptr(a), a.size))
+
+    def info(self):
+        s, w = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib.lat_on_get_info(self._h, ctypes.byref(s), ctypes.byref(w)))
+        return {"seed": s.value, "sweeps": w.value}
+
+    def profile(self, reps) -> float:
+        """Average milliseconds per pass (half a sweep) over `reps` sweeps."""
+        ms = ctypes.c_double()
+        _check(lib.lat_on_profile(self._h, int(reps), ctypes.byref(ms)))
+        return ms.value

@@ -499,6 +499,12 @@ void destroy_handle(lat_ctx* h) {
 
 }  // namespace
 
+// Error reporting for the other host sources of the library (O(N) fields).
+int lat_internal_fail(int code, const char* msg) {
+    g_err = msg;
+    return code;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================

@@ -19,3 +19,5 @@ hipError_t lat_launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint
 // heat-bath counters are advanced.
 hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t** counters, int grid, int block,
                             hipStream_t st);
+// Sets the calling thread's error message (lat_last_error) and returns code.
+int lat_internal_fail(int code, const char* msg);

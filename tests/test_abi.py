@@ -117,3 +117,27 @@ def test_batch_rejects_frozen_links_without_a_device():
     with pytest.raises(P.LatError) as e:
         P.Batch([dict(group=3, dims=(4, 4, 4, 4), beta=5.7)], frozen=P.FROZEN_T0)
     assert e.value.code == P.EUNSUPPORTED
+
+
+def test_o_n_layout_and_rejections_without_a_device():
+    import paper_1310_7087_amd as P
+    V = 32 ** 4
+    for st, b in ((P.F64, 8), (P.F32, 4)):
+        n = P.on_device_bytes(4, (32, 32, 32, 32), storage=st)
+        assert 4 * V * b <= n < 4 * V * b + (1 << 20)
+    # RANLUX keeps 25 words per site
+    assert P.on_device_bytes(4, (8, 8, 8, 8), rng=P.RNG_RANLUX) - P.on_device_bytes(4, (8, 8, 8, 8)) >= 100 * 8 ** 4
+    assert P.on_device_bytes(5, (4, 4, 4, 4)) == 0
+    assert P.on_device_bytes(4, (3, 4, 4, 4)) == 0
+    assert P.on_device_bytes(4, (4, 4, 4, 4), storage=P.F32_C12) == 0
+    assert P.on_device_bytes(4, (4, 4, 4, 4), rng=P.RNG_MRG32K3A) == 0
+    assert P.on_device_bytes(4, (4, 4, 4, 4), nhit=1001) == 0
+    for kw, code in (({"ncomp": 0}, P.EINVAL), ({"dims": (4, 4, 4, 5)}, P.EINVAL), ({"lam": -0.1}, P.EINVAL),
+                     ({"delta": 0.0}, P.EINVAL), ({"kappa": float("nan")}, P.EINVAL),
+                     ({"storage": P.F64_C12}, P.EUNSUPPORTED), ({"rng": P.RNG_MRG32K3A}, P.EUNSUPPORTED),
+                     ({"nhit": 0}, P.EINVAL)):
+        args = dict(ncomp=4, dims=(4, 4, 4, 4), kappa=0.1, lam=0.1, delta=1.0)
+        args.update(kw)
+        with pytest.raises(P.LatError) as e:
+            P.ONField(args.pop("ncomp"), args.pop("dims"), args.pop("kappa"), args.pop("lam"), **args)
+        assert e.value.code == code, kw

@@ -1,0 +1,151 @@
+"""GPU parity of the O(N) phi^4 path (lat_on_* through the C ABI) with the
+FP64 CPU oracle on the same seeded inputs.
+
+Both sides run the same multi-hit Metropolis chain with the same uniforms;
+an accept decision could differ only where the acceptance uniform lies
+within rounding of exp(-dS) (probability ~1e-16 per hit), so FP64 fields
+agree to 1e-12 (max abs over all sites and components) and the accepted-hit
+counts agree exactly.  FP32 storage rounds the field after every update:
+values agree to 1e-5 except at the rare sites where a decision flipped
+(at most 1% of the sites here, typically none)."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1310_7087_amd")
+
+TOL64 = 1e-12
+
+# (N, dims, kappa, lambda, h, delta, start, nhit)
+CASES = [
+    (4, (8, 8, 8, 8), 0.3, 1.0, 0.0, 1.0, O.HOT, 100),
+    (1, (6, 4, 10, 2), 0.2, 0.5, 0.1, 1.5, O.COLD, 20),
+    (2, (4, 6, 8, 4), -0.1, 0.0, -0.3, 0.8, O.HOT, 10),
+    (3, (2, 2, 2, 2), 0.25, 2.0, 0.4, 1.2, O.HOT, 7),
+    (4, (10, 2, 4, 6), 0.31, 0.7, 0.05, 0.9, O.COLD, 50),
+]
+
+
+def pair(n, dims, kappa, lam, h, delta, start, nhit, rng=O.RNG_PHILOX, seed=3, storage=0, rng_const=0.5,
+         lattice_id=0, block_size=0):
+    g = P.ONField(n, dims, kappa, lam, h, delta, storage=storage, rng=rng, rng_const=rng_const, seed=seed,
+                  nhit=nhit, lattice_id=lattice_id, start=start, block_size=block_size)
+    o = O.ONField(n, dims, kappa, lam, h, delta, rng=rng, rng_const=rng_const, seed=seed, nhit=nhit,
+                  lattice_id=lattice_id, start=start)
+    return g, o
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_start_and_sweeps_match_oracle(case):
+    g, o = pair(*case)
+    assert np.array_equal(g.get_field(), o.get_field())  # starts are exact in FP64
+    for k in (1, 2):
+        g.sweep(k)
+        o.sweep(k)
+        assert np.abs(g.get_field() - o.get_field()).max() <= TOL64, case
+        assert g.acceptance() == o.acceptance()
+        assert np.abs(g.measure() - o.measure()).max() <= TOL64
+    g.close()
+
+
+@pytest.mark.parametrize("n", [1, 4])
+def test_ranlux_streams_match_oracle(n):
+    g, o = pair(n, (8, 4, 4, 6), 0.28, 0.9, 0.1, 1.1, O.HOT, 30, rng=O.RNG_RANLUX, seed=77)
+    assert np.array_equal(g.get_field(), o.get_field())
+    g.sweep(2)
+    o.sweep(2)
+    assert np.abs(g.get_field() - o.get_field()).max() <= TOL64
+    assert g.acceptance() == o.acceptance()
+    g.close()
+
+
+def test_constant_generator_walk():
+    """The hand-derived walk of the oracle's pins: every site ends at
+    (0, -1, -1, -1) after four accepted hits."""
+    g = P.ONField(4, (4, 4, 2, 2), 0.0, 0.0, 0.0, 0.5, rng=P.RNG_CONST, rng_const=0.25, nhit=10, start=P.COLD)
+    g.sweep(1)
+    assert np.array_equal(g.get_field(), np.tile([0.0, -1.0, -1.0, -1.0], (64, 1)))
+    assert g.acceptance() == 0.4
+    g.close()
+
+
+@pytest.mark.parametrize("block", [64, 128])
+def test_work_group_size_does_not_change_results(block):
+    a = P.ONField(4, (6, 4, 10, 2), 0.3, 1.0, 0.2, 1.0, seed=5, nhit=40)
+    b = P.ONField(4, (6, 4, 10, 2), 0.3, 1.0, 0.2, 1.0, seed=5, nhit=40, block_size=block)
+    a.sweep(3)
+    b.sweep(3)
+    assert np.array_equal(a.get_field(), b.get_field())
+    assert a.acceptance() == b.acceptance()
+    a.close()
+    b.close()
+
+
+def test_run_series_equals_stepwise_measurements():
+    a = P.ONField(2, (8, 8, 4, 4), 0.2, 0.3, 0.1, 1.2, seed=9, nhit=10)
+    b = P.ONField(2, (8, 8, 4, 4), 0.2, 0.3, 0.1, 1.2, seed=9, nhit=10)
+    series = a.run(12, 3)
+    want = []
+    for _ in range(4):
+        b.sweep(3)
+        want.append(b.measure())
+    assert series.shape == (4, 7)
+    assert np.array_equal(series, np.array(want))
+    assert a.info()["sweeps"] == 12
+    a.close()
+    b.close()
+
+
+def test_longer_chain_matches_oracle():
+    g, o = pair(4, (8, 8, 8, 8), 0.3, 1.0, 0.0, 1.0, O.HOT, 100, seed=21)
+    g.sweep(20)
+    o.sweep(20)
+    assert np.abs(g.get_field() - o.get_field()).max() <= TOL64
+    g.close()
+
+
+def test_f32_storage_close_to_oracle():
+    g, o = pair(4, (8, 8, 8, 8), 0.3, 1.0, 0.0, 1.0, O.HOT, 100, storage=P.F32, seed=4)
+    assert np.array_equal(g.get_field(), o.get_field())  # the hot start is exact in FP32
+    g.sweep(1)
+    o.sweep(1)
+    d = np.abs(g.get_field() - o.get_field()).max(axis=1)
+    assert (d > 1e-5).mean() <= 0.01
+    assert np.median(d) < 1e-6
+    m = g.measure() - o.measure()
+    assert np.abs(m).max() < 1e-4
+    g.close()
+
+
+def test_set_and_get_field_round_trip():
+    g = P.ONField(3, (4, 4, 4, 2), 0.1, 0.2, seed=2, nhit=5)
+    phi = np.random.default_rng(0).standard_normal((g.V, 3))
+    g.set_field(phi)
+    assert np.array_equal(g.get_field(), phi)
+    o = O.ONField(3, (4, 4, 4, 2), 0.1, 0.2, seed=2, nhit=5)
+    o.set_field(phi)
+    g.sweep(2)
+    o.sweep(2)
+    assert np.abs(g.get_field() - o.get_field()).max() <= TOL64
+    g.close()
+
+
+def test_time_seed_is_reported():
+    g = P.ONField(1, (2, 2, 2, 2), 0.1, 0.1, seed=0, nhit=1)
+    assert g.info()["seed"] != 0
+    g.close()
+
+
+def test_full_size_o4_32():
+    """An O(4) lattice of the paper's Table 1 (32^4, NHIT = 100): one sweep
+    from the hot start, every site against the oracle."""
+    g, o = pair(4, (32, 32, 32, 32), 0.3, 1.0, 0.0, 1.0, O.HOT, 100, seed=13)
+    g.sweep(1)
+    o.sweep(1)
+    assert np.abs(g.get_field() - o.get_field()).max() <= TOL64
+    assert g.acceptance() == o.acceptance()
+    assert np.abs(g.measure() - o.measure()).max() <= TOL64
+    g.close()
