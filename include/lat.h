@@ -13,6 +13,8 @@
  * checkerboard (pseudo-)heat bath (Sec. 3.3); selectable generator with one
  * seed parameter, 0 meaning "system time" (Sec. 3.4); hot start, NHIT = 10
  * tries and reunitarisation (Sec. 5); periodic state saving (Sec. 3.1).
+ * The lat_on_* calls at the end run the paper's second model family, O(N)
+ * models (N-vector fields on the sites, Metropolis update, Sec. 3.3 and 5).
  *
  * Conventions shared by every call:
  *   - Extents Nx, Ny, Nz, Nt are even and >= 2 (the checkerboard with
@@ -363,6 +365,19 @@ int lat_on_get_info(lat_on_t h, uint64_t* seed_used, uint64_t* sweeps_done);
  * handle's stream and returns the average duration of one pass (half a
  * sweep) in milliseconds.  The field advances as with lat_on_sweep. */
 int lat_on_profile(lat_on_t h, int reps, double* ms_per_pass);
+
+/*
+ * Portable checkpoint of an O(N) field (the paper's periodic state saving,
+ * Sec. 3.1; little-endian, FNV-1a checksummed): parameters, sweep counter,
+ * the canonical FP64 field and, for RANLUX, every site's generator state.
+ * lat_on_load creates a new handle (storage, stream and device buffer from
+ * opt, or the saved storage if opt is NULL; generator, seed, NHIT and
+ * lattice id always from the file) that continues the saved chain exactly.
+ * LAT_EIO if the file cannot be read or written, LAT_ECORRUPT on a bad
+ * header, size or checksum.
+ */
+int lat_on_save(lat_on_t h, const char* path);
+int lat_on_load(lat_on_t* out, const char* path, const lat_options* opt);
 
 /* Releases the handle; NULL is a no-op. */
 int lat_on_destroy(lat_on_t h);

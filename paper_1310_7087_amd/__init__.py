@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import struct
 
 import numpy as np
 
@@ -111,7 +112,9 @@ def _load():
     L.lat_on_get_info.argtypes = [vp, P(u64), P(u64)]
     L.lat_on_profile.argtypes = [vp, i, P(d)]
     L.lat_on_destroy.argtypes = [vp]
-    for name in ("lat_on_create", "lat_on_sweep", "lat_on_measure", "lat_on_run", "lat_on_acceptance",
+    L.lat_on_save.argtypes = [vp, ctypes.c_char_p]
+    L.lat_on_load.argtypes = [P(vp), ctypes.c_char_p, P(Options)]
+    for name in ("lat_on_save", "lat_on_load", "lat_on_create", "lat_on_sweep", "lat_on_measure", "lat_on_run", "lat_on_acceptance",
                  "lat_on_get_field", "lat_on_set_field", "lat_on_get_info", "lat_on_profile", "lat_on_destroy"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_set_links",
@@ -415,6 +418,27 @@ class ONField:
         s, w = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib.lat_on_get_info(self._h, ctypes.byref(s), ctypes.byref(w)))
         return {"seed": s.value, "sweeps": w.value}
+
+    def save(self, path) -> None:
+        _check(lib.lat_on_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, storage=None, stream=None):
+        """Continue a saved O(N) chain (storage from the file unless given)."""
+        with open(path, "rb") as fh:
+            head = struct.unpack("<8s12I", fh.read(8 + 4 * 12))
+        self = cls.__new__(cls)
+        self.n = int(head[2])
+        self.dims = tuple(int(x) for x in head[3:7])
+        self.V = int(np.prod(self.dims))
+        h_ = ctypes.c_void_p()
+        if storage is None and stream is None:
+            _check(lib.lat_on_load(ctypes.byref(h_), os.fsencode(path), None))
+        else:
+            o = make_options(storage=F64 if storage is None else storage, stream=stream)
+            _check(lib.lat_on_load(ctypes.byref(h_), os.fsencode(path), ctypes.byref(o)))
+        self._h = h_
+        return self
 
     def profile(self, reps) -> float:
         """Average milliseconds per pass (half a sweep) over `reps` sweeps."""

@@ -114,35 +114,51 @@ __global__ void __launch_bounds__(256) on_pass(OnArgs a) {
             d.idx = 0;
         }
         double s0 = local_action<N>(a, F, ph);
+        // delta (2u - 1) for the 24-bit draw v, u = (v + 1/2) 2^-24, is
+        // (2v + 1 - 2^24) (delta 2^-24): an exact integer times an exact
+        // scale, rounded once, as the plain formula is
+        const double dstep = a.delta * (1.0 / 16777216.0);
         for (int k = 0; k < a.nhit; ++k) {
-            double r[N], uacc;
-            if constexpr (RNG == LAT_RNG_PHILOX_I) {
-                const u4 o = philox10({site, a.lat_id, a.sweep, (uint32_t)k}, a.key0, a.key1);
-                const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+            double tr[N], uacc;
+            if constexpr (RNG == LAT_RNG_CONST_I) {
 #pragma unroll
-                for (int j = 0; j < N; ++j) r[j] = u24(w[j]);
-                uacc = accept_u24(o.x, o.y, o.z);
-            } else if constexpr (RNG == LAT_RNG_RANLUX_I) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) r[j] = u24(d.next() << 8);
-                uacc = u24(d.next() << 8);
-            } else {
-#pragma unroll
-                for (int j = 0; j < N; ++j) r[j] = a.rng_const;
+                for (int j = 0; j < N; ++j) tr[j] = ph[j] + a.delta * (2.0 * a.rng_const - 1.0);
                 uacc = a.rng_const;
-            }
-            double tr[N];
+            } else {
+                uint32_t v[N];
+                if constexpr (RNG == LAT_RNG_PHILOX_I) {
+                    const u4 o = philox10({site, a.lat_id, a.sweep, (uint32_t)k}, a.key0, a.key1);
+                    const uint32_t w[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-            for (int j = 0; j < N; ++j) tr[j] = ph[j] + a.delta * (2.0 * r[j] - 1.0);
+                    for (int j = 0; j < N; ++j) v[j] = w[j] >> 8;
+                    uacc = accept_u24(o.x, o.y, o.z);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < N; ++j) v[j] = d.next();
+                    uacc = u24(d.next() << 8);
+                }
+#pragma unroll
+                for (int j = 0; j < N; ++j) tr[j] = ph[j] + (double)((int)(2u * v[j] + 1u) - (1 << 24)) * dstep;
+            }
             const double s1 = local_action<N>(a, F, tr);
             const double dS = s1 - s0;
-            // exp(-dS) >= 1 > uacc whenever dS <= 0: only uphill steps need it
-            if (dS <= 0.0 || uacc < exp(-dS)) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) ph[j] = tr[j];
-                s0 = s1;
-                ++accepted;
+            // accept iff uacc < exp(-dS).  exp(-dS) >= 1 > uacc when dS <= 0.
+            // Otherwise an FP32 exponential (relative error < 1e-5 for every
+            // dS where exp(-dS) can exceed the smallest uacc, 2^-25) decides
+            // all but the draws within 1e-4 of the threshold, which take the
+            // FP64 exponential: the decision is that of the FP64 test.
+            bool acc = true;
+            if (dS > 0.0) {
+                const double e = (double)__expf((float)(-dS));
+                if (uacc > e * (1.0 + 1e-4))
+                    acc = false;
+                else if (uacc >= e * (1.0 - 1e-4))
+                    acc = uacc < exp(-dS);
             }
+#pragma unroll
+            for (int j = 0; j < N; ++j) ph[j] = acc ? tr[j] : ph[j];
+            s0 = acc ? s1 : s0;
+            accepted += acc ? 1u : 0u;
         }
 #pragma unroll
         for (int k = 0; k < N; ++k) plane<T>(a.field, vp, N, p, k)[s] = (T)ph[k];
@@ -280,6 +296,22 @@ __global__ void __launch_bounds__(256) on_convert(OnArgs a, int N, int to_dev, d
             pl[s] = (T)canon[i * N + k];
         else
             canon[i * N + k] = (double)pl[s];
+    }
+}
+
+// RANLUX states: device planes [parity][word][vp] <-> canonical [site][25]
+__global__ void __launch_bounds__(256) on_rl_convert(OnArgs a, int to_dev, uint32_t* canon) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= 2 * a.g.vh) return;
+    const int p = j >= a.g.vh ? 1 : 0;
+    const int64_t s = j - p * a.g.vh;
+    const int64_t i = canon_index(a.g, decode(a.g, s, p));
+    for (int w = 0; w < 25; ++w) {
+        uint32_t* pl = a.rl + ((int64_t)p * 25 + w) * a.g.vh_pad;
+        if (to_dev)
+            pl[s] = canon[i * 25 + w];
+        else
+            canon[i * 25 + w] = pl[s];
     }
 }
 
@@ -515,6 +547,44 @@ int create_device(lat_on_ctx* c, const lat_options& o) {
     return LAT_OK;
 }
 
+// Copies the RANLUX states between the device planes and a host array in
+// canonical site order (25 words per site); synchronises.
+int rl_transfer(lat_on_ctx* c, uint32_t* host, bool to_dev) {
+    const size_t n = (size_t)c->V() * 25;
+    uint32_t* dev = nullptr;
+    ON_TRY(hipMalloc((void**)&dev, n * 4));
+    hipError_t e = hipSuccess;
+    if (to_dev) e = hipMemcpyAsync(dev, host, n * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(on_rl_convert, dim3((unsigned)((c->V() + 255) / 256)), dim3(256), 0, c->stream,
+                           on_args(c, 0), to_dev ? 1 : 0, dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !to_dev) e = hipMemcpyAsync(host, dev, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return lat_internal_fail(LAT_EDEVICE, hip_msg("RANLUX state transfer", e).c_str());
+    return LAT_OK;
+}
+
+const char ON_MAGIC[8] = {'L', 'A', 'T', 'O', 'N', 'C', 'K', '1'};
+
+struct OnCkptHeader {
+    char magic[8];
+    uint32_t version, ncomp, dims[4], storage, rng, start, nhit, lat_id, reserved;
+    double kappa, lambda, h, delta, rng_const;
+    uint64_t seed, sweeps, n_doubles, n_words;
+};
+
+uint64_t on_fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -700,6 +770,115 @@ int lat_on_profile(lat_on_t c, int reps, double* ms_per_pass) {
     if (rc) return rc;
     if (e != hipSuccess) return lat_internal_fail(LAT_EDEVICE, hip_msg("lat_on_profile", e).c_str());
     *ms_per_pass = (double)ms / (2.0 * reps);
+    return LAT_OK;
+}
+
+int lat_on_save(lat_on_t c, const char* path) {
+    if (!c || !path) return lat_internal_fail(LAT_EINVAL, "NULL argument");
+    std::vector<double> field((size_t)c->V() * c->n);
+    int rc = lat_on_get_field(c, field.data(), field.size());
+    if (rc) return rc;
+    std::vector<uint32_t> words;
+    if (c->rng == LAT_RNG_RANLUX) {
+        words.resize((size_t)c->V() * 25);
+        if ((rc = rl_transfer(c, words.data(), false))) return rc;
+    }
+    OnCkptHeader hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, ON_MAGIC, 8);
+    hd.version = 1;
+    hd.ncomp = (uint32_t)c->n;
+    hd.dims[0] = (uint32_t)c->g.nx;
+    hd.dims[1] = (uint32_t)c->g.ny;
+    hd.dims[2] = (uint32_t)c->g.nz;
+    hd.dims[3] = (uint32_t)c->g.nt;
+    hd.storage = (uint32_t)c->storage;
+    hd.rng = (uint32_t)c->rng;
+    hd.start = (uint32_t)c->start;
+    hd.nhit = (uint32_t)c->nhit;
+    hd.lat_id = c->lat_id;
+    hd.kappa = c->kappa;
+    hd.lambda = c->lambda;
+    hd.h = c->h;
+    hd.delta = c->delta;
+    hd.rng_const = c->rng_const;
+    hd.seed = c->seed;
+    hd.sweeps = c->sweeps;
+    hd.n_doubles = field.size();
+    hd.n_words = words.size();
+    uint64_t sum = 1469598103934665603ull;
+    sum = on_fnv1a(sum, &hd, sizeof hd);
+    sum = on_fnv1a(sum, field.data(), field.size() * sizeof(double));
+    if (!words.empty()) sum = on_fnv1a(sum, words.data(), words.size() * 4);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return lat_internal_fail(LAT_EIO, ("cannot open " + tmp).c_str());
+    bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1;
+    ok = ok && std::fwrite(field.data(), sizeof(double), field.size(), f) == field.size();
+    if (!words.empty()) ok = ok && std::fwrite(words.data(), 4, words.size(), f) == words.size();
+    ok = ok && std::fwrite(&sum, sizeof sum, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return lat_internal_fail(LAT_EIO, (std::string("write of ") + path + " failed").c_str());
+    }
+    return LAT_OK;
+}
+
+int lat_on_load(lat_on_t* out, const char* path, const lat_options* opt) {
+    if (!out || !path) return lat_internal_fail(LAT_EINVAL, "NULL argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return lat_internal_fail(LAT_EIO, (std::string("cannot open ") + path).c_str());
+    OnCkptHeader hd;
+    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, ON_MAGIC, 8) != 0 || hd.version != 1 ||
+        hd.ncomp < 1 || hd.ncomp > 4) {
+        std::fclose(f);
+        return lat_internal_fail(LAT_ECORRUPT, "not an O(N) checkpoint");
+    }
+    const uint64_t V = (uint64_t)hd.dims[0] * hd.dims[1] * hd.dims[2] * hd.dims[3];
+    if (V == 0 || V > ((uint64_t)1 << 32) || hd.n_doubles != V * hd.ncomp ||
+        hd.n_words != (hd.rng == LAT_RNG_RANLUX ? V * 25 : 0)) {
+        std::fclose(f);
+        return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint sizes do not match its header");
+    }
+    std::vector<double> field(hd.n_doubles);
+    std::vector<uint32_t> words(hd.n_words);
+    uint64_t sum = 0;
+    bool ok = std::fread(field.data(), sizeof(double), field.size(), f) == field.size();
+    if (!words.empty()) ok = ok && std::fread(words.data(), 4, words.size(), f) == words.size();
+    ok = ok && std::fread(&sum, sizeof sum, 1, f) == 1;
+    std::fclose(f);
+    if (!ok) return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint is truncated");
+    uint64_t want = 1469598103934665603ull;
+    want = on_fnv1a(want, &hd, sizeof hd);
+    want = on_fnv1a(want, field.data(), field.size() * sizeof(double));
+    if (!words.empty()) want = on_fnv1a(want, words.data(), words.size() * 4);
+    if (want != sum) return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint checksum mismatch");
+    lat_options o;
+    lat_default_options(&o);
+    if (opt) o = *opt;
+    else o.storage = (int)hd.storage;
+    o.rng = (int)hd.rng;
+    o.rng_const = hd.rng_const;
+    o.start = LAT_COLD;  // replaced below
+    o.seed = hd.seed;
+    o.nhit = (int)hd.nhit;
+    o.lattice_id = hd.lat_id;
+    lat_on_t c = nullptr;
+    int rc = lat_on_create(&c, (int)hd.ncomp, (int)hd.dims[0], (int)hd.dims[1], (int)hd.dims[2], (int)hd.dims[3],
+                           hd.kappa, hd.lambda, hd.h, hd.delta, &o);
+    if (rc) return rc;
+    c->start = (int)hd.start;
+    c->sweeps = hd.sweeps;
+    rc = lat_on_set_field(c, field.data(), field.size());
+    if (!rc && !words.empty()) rc = rl_transfer(c, words.data(), true);
+    if (rc) {
+        const std::string keep = lat_last_error();
+        destroy(c);
+        return lat_internal_fail(rc, keep.c_str());
+    }
+    *out = c;
     return LAT_OK;
 }
 

@@ -149,3 +149,36 @@ def test_full_size_o4_32():
     assert g.acceptance() == o.acceptance()
     assert np.abs(g.measure() - o.measure()).max() <= TOL64
     g.close()
+
+
+@pytest.mark.parametrize("rng", [P.RNG_PHILOX, P.RNG_RANLUX])
+def test_checkpoint_continues_the_chain(tmp_path, rng):
+    """N sweeps straight equal N/2 + save + load + N/2, bit for bit."""
+    a = P.ONField(4, (6, 4, 8, 2), 0.3, 1.0, 0.1, 0.55, rng=rng, seed=8, nhit=25)
+    b = P.ONField(4, (6, 4, 8, 2), 0.3, 1.0, 0.1, 0.55, rng=rng, seed=8, nhit=25)
+    a.sweep(4)
+    b.sweep(2)
+    path = tmp_path / "o4.ckpt"
+    b.save(path)
+    b.close()
+    c = P.ONField.load(path)
+    assert c.info()["sweeps"] == 2 and c.dims == (6, 4, 8, 2)
+    c.sweep(2)
+    assert np.array_equal(a.get_field(), c.get_field())
+    assert a.acceptance() == c.acceptance()
+    a.close()
+    c.close()
+
+
+def test_checkpoint_rejects_a_damaged_file(tmp_path):
+    f = P.ONField(2, (4, 4, 2, 2), 0.2, 0.5, seed=1, nhit=3)
+    path = tmp_path / "o2.ckpt"
+    f.save(path)
+    data = bytearray(path.read_bytes())
+    data[200] ^= 1
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(bytes(data))
+    with pytest.raises(P.LatError) as e:
+        P.ONField.load(bad)
+    assert e.value.code == P.ECORRUPT
+    f.close()
