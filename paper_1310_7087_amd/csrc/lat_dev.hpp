@@ -350,13 +350,18 @@ struct draws<LAT_RNG_MRG_I> {
 // last 24 outputs oldest first, so one in-place round of 24 steps reads
 // x_{n-10} at b[(k+14) % 24] (an old value for k < 10, a new one after) and
 // x_{n-24} at b[k], and leaves b oldest first again.
+// One step: with 24-bit operands in 32-bit registers the borrow out of the
+// 32-bit subtraction a - b - c is exactly the generator's carry (a < b + c),
+// so a subtract-with-borrow instruction yields both, and a mask the value.
+LAT_DEV uint32_t swb_step(uint32_t a, uint32_t b, uint32_t& c) {
+    unsigned int borrow;
+    const uint32_t y = __builtin_subc(a, b, c, &borrow);
+    c = borrow;
+    return y & 0xFFFFFFu;
+}
 LAT_DEV void swb_round(uint32_t (&b)[24], uint32_t& c) {
 #pragma unroll
-    for (int k = 0; k < 24; ++k) {
-        const int32_t y = (int32_t)b[(k + 14) % 24] - (int32_t)b[k] - (int32_t)c;
-        c = y < 0 ? 1u : 0u;
-        b[k] = (uint32_t)y & 0xFFFFFFu;
-    }
+    for (int k = 0; k < 24; ++k) b[k] = swb_step(b[(k + 14) % 24], b[k], c);
 }
 // From the last delivered block to the next one: skip the other 199 outputs
 // of the current group of 223 (8 rounds and 7 steps, after which b is
@@ -366,11 +371,7 @@ LAT_DEV void ranlux_next_block(uint32_t (&b)[24], uint32_t& c, bool skip) {
     if (skip) {
         for (int r = 0; r < 8; ++r) swb_round(b, c);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            const int32_t y = (int32_t)b[k + 14] - (int32_t)b[k] - (int32_t)c;
-            c = y < 0 ? 1u : 0u;
-            b[k] = (uint32_t)y & 0xFFFFFFu;
-        }
+        for (int k = 0; k < 7; ++k) b[k] = swb_step(b[k + 14], b[k], c);
         uint32_t t[24];
 #pragma unroll
         for (int j = 0; j < 24; ++j) t[j] = b[(j + 7) % 24];
