@@ -230,7 +230,15 @@ def run_batch(P, sweeps: int = 10, precision_sweeps: int = 1000):
         s.close()
     log(f"[batch] F32 batched {rates['f32_batched']:.3e}, F64 batched {rates['f64_batched']:.3e}, "
         f"F64 one by one {rates['f64_one_by_one']:.3e} link updates/s")
+    # algorithmic bytes: 9 b per link update (4.5 V b per pass), b by group and storage
+    bpl = {("f32", 3): 72, ("f32", 2): 16, ("f64", 3): 144, ("f64", 2): 32}
+    frac = {}
+    for name in ("f32_batched", "f64_batched"):
+        per_update = sum(4 * volume(w.dims) * 9 * bpl[(name[:3], w.group)] for w in ws) / links
+        frac[name] = {"algorithmic_GBs": rates[name] * per_update / 1e9,
+                      "hbm_fraction": rates[name] * per_update / 1e9 / HBM_PEAK_GBS}
     out = {"lattices": len(ws), "total_links": links, "sweeps": sweeps, "launch_shapes": shapes,
+           "roofline": frac,
            "f32_batched_link_updates_per_s": rates["f32_batched"],
            "f64_batched_link_updates_per_s": rates["f64_batched"],
            "f64_one_by_one_link_updates_per_s": rates["f64_one_by_one"],

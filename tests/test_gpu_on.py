@@ -182,3 +182,39 @@ def test_checkpoint_rejects_a_damaged_file(tmp_path):
         P.ONField.load(bad)
     assert e.value.code == P.ECORRUPT
     f.close()
+
+
+def _binned(x, nbins=20):
+    x = np.asarray(x)
+    b = x[: len(x) // nbins * nbins].reshape(nbins, -1).mean(axis=1)
+    return b.mean(), b.std(ddof=1) / np.sqrt(nbins)
+
+
+@pytest.mark.parametrize("storage,rng", [(0, O.RNG_PHILOX), (1, O.RNG_RANLUX)])
+def test_long_run_matches_exact_one_site_density(storage, rng):
+    """kappa = 0 on the GPU itself: the chain samples the one-site density,
+    whose moments come from quadrature (independent of both implementations)."""
+    from test_oracle_on import one_site_moments
+    f = P.ONField(4, (8, 8, 8, 8), 0.0, 0.5, 0.3, 1.4, storage=storage, rng=rng, seed=19, nhit=6)
+    f.sweep(50)
+    s = f.run(2000, 1)
+    p2, q, m0 = one_site_moments(4, 0.5, 0.3)
+    for col, want in ((0, p2), (2, q), (3, m0)):
+        got, err = _binned(s[:, col])
+        assert abs(got - want) < 4.5 * err + 2e-4, (col, got, want, err)
+    f.close()
+
+
+def test_long_run_matches_free_field_propagator():
+    """lambda = 0 on the GPU: <phi^2>, the link product and <phi_0> of the
+    free lattice field, exactly known on the finite lattice."""
+    from test_oracle_on import free_field
+    dims = (8, 4, 6, 4)
+    f = P.ONField(2, dims, 0.1, 0.0, 0.2, 1.3, seed=5, nhit=8)
+    f.sweep(200)
+    s = f.run(4000, 1)
+    phi2, link, m = free_field(dims, 2, 0.1, 0.2)
+    for col, want in ((0, phi2), (1, link), (3, m)):
+        got, err = _binned(s[:, col])
+        assert abs(got - want) < 4.5 * err + 2e-4, (col, got, want, err)
+    f.close()
