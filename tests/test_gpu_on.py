@@ -8,6 +8,8 @@ agree to 1e-12 (max abs over all sites and components) and the accepted-hit
 counts agree exactly.  FP32 storage rounds the field after every update:
 values agree to 1e-5 except at the rare sites where a decision flipped
 (at most 1% of the sites here, typically none)."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -217,4 +219,32 @@ def test_long_run_matches_free_field_propagator():
     for col, want in ((0, phi2), (1, link), (3, m)):
         got, err = _binned(s[:, col])
         assert abs(got - want) < 4.5 * err + 2e-4, (col, got, want, err)
+    f.close()
+
+
+def test_acceptance_before_a_sweep_is_a_state_error():
+    f = P.ONField(1, (2, 2, 2, 2), 0.1, 0.1, seed=1, nhit=2)
+    with pytest.raises(P.LatError) as e:
+        f.acceptance()
+    assert e.value.code == P.ESTATE
+    f.sweep(1)
+    assert 0.0 <= f.acceptance() <= 1.0
+    f.close()
+
+
+def test_f32_storage_rounds_set_values():
+    f = P.ONField(2, (4, 2, 2, 2), 0.1, 0.1, storage=P.F32, seed=1, nhit=2)
+    phi = np.random.default_rng(1).standard_normal((f.V, 2))
+    f.set_field(phi)
+    assert np.array_equal(f.get_field(), phi.astype(np.float32).astype(np.float64))
+    f.close()
+
+
+def test_wrong_buffer_sizes_are_rejected():
+    f = P.ONField(3, (2, 2, 2, 2), 0.1, 0.1, seed=1, nhit=2)
+    buf = np.zeros(f.V * 2)
+    ptr = buf.ctypes.data_as(ctypes.c_void_p)
+    assert P.lib.lat_on_set_field(f._h, ptr, buf.size) == P.EINVAL
+    assert P.lib.lat_on_get_field(f._h, ptr, buf.size) == P.EINVAL
+    assert P.lib.lat_on_get_field(f._h, None, f.V * 3) == P.EINVAL
     f.close()
