@@ -309,8 +309,8 @@ size_t lat_on_device_bytes(int ncomp, int Nx, int Ny, int Nz, int Nt, const lat_
  *   ncomp: N in 1..4; kappa: hopping parameter (finite); lambda >= 0;
  *   h: source along component 0; delta > 0: proposal half-width.
  *   opt: storage LAT_F64 or LAT_F32 (field storage; all update and
- *   reduction arithmetic is FP64 in both), rng LAT_RNG_PHILOX,
- *   LAT_RNG_RANLUX or LAT_RNG_CONST (others LAT_EUNSUPPORTED), nhit = hits
+ *   reduction arithmetic is FP64 in both), rng any of the four generators
+ *   (MRG32k3a: 1 <= seed < 4294944443, else LAT_EINVAL), nhit = hits
  *   per site and sweep 1..1000 (NULL opt: 100, the paper's value), seed,
  *   lattice_id, start, stream, device_buffer/device_bytes and block_size as
  *   for lat_create; frozen must be LAT_FROZEN_NONE; the tile, layout and
@@ -321,7 +321,9 @@ size_t lat_on_device_bytes(int ncomp, int Nx, int Ny, int Nz, int Nt, const lat_
  * hot start uses counter (site, lattice_id, 0, 0xFFFFFFFF).  RANLUX (seeded
  * as for lat_create): every site update begins a new block, each hit takes
  * N values then the acceptance value; the hot start takes the first N values
- * of the first block.
+ * of the first block.  MRG32k3a (site streams 2^127 apart, as for
+ * lat_create): drawn in sequence, the hot start N values, each hit N values
+ * then the acceptance value.
  */
 int lat_on_create(lat_on_t* out, int ncomp, int Nx, int Ny, int Nz, int Nt, double kappa, double lambda,
                   double h, double delta, const lat_options* opt);
@@ -369,7 +371,8 @@ int lat_on_profile(lat_on_t h, int reps, double* ms_per_pass);
 /*
  * Portable checkpoint of an O(N) field (the paper's periodic state saving,
  * Sec. 3.1; little-endian, FNV-1a checksummed): parameters, sweep counter,
- * the canonical FP64 field and, for RANLUX, every site's generator state.
+ * the canonical FP64 field and, for RANLUX and MRG32k3a, every site's
+ * generator state.
  * lat_on_load creates a new handle (storage, stream and device buffer from
  * opt, or the saved storage if opt is NULL; generator, seed, NHIT and
  * lattice id always from the file) that continues the saved chain exactly.

@@ -86,6 +86,8 @@ def lib():
         L.orc_on_set_field.argtypes = [vp, vp]
         L.orc_on_sweeps.argtypes = [vp]
         L.orc_on_sweeps.restype = u64
+        L.orc_on_get_mrg_states.argtypes = [vp, vp]
+        L.orc_on_get_mrg_states.restype = i
         L.orc_on_acceptance.argtypes = [vp]
         L.orc_on_acceptance.restype = d
         _lib = L
@@ -288,3 +290,9 @@ class ONField:
 
     def acceptance(self) -> float:
         return float(lib().orc_on_acceptance(self._h))
+
+    def mrg_states(self) -> np.ndarray:
+        out = np.empty((self.V, 6), dtype=np.uint32)
+        if lib().orc_on_get_mrg_states(self._h, _ptr(out)) != 0:
+            raise ValueError("not an MRG32k3a field")
+        return out

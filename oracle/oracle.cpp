@@ -905,9 +905,12 @@ int orc_update_link(int group, double beta, int nhit, int kind, int reunit, cons
  *           w0, w1, w2 (high to low);
  *   RANLUX: every site update begins a new block; per hit N values for r
  *           then one for u_acc;
+ *   MRG32k3a: the site's stream (2^127 apart, as for the SU(N) links),
+ *           sequentially: per hit N values for r then one for u_acc;
  *   constant: every uniform = c.
  * Starts: cold phi = (1, 0, ..., 0); hot phi_a = 2 u_a - 1 with Philox counter
- * (i, lattice_id, 0, 0xFFFFFFFF), or the first N values of a RANLUX block.
+ * (i, lattice_id, 0, 0xFFFFFFFF), the first N values of a RANLUX block, or
+ * the first N values of the MRG32k3a stream.
  */
 struct orc_on {
     int n;
@@ -923,6 +926,7 @@ struct orc_on {
     int64_t accepted_last;  // accepted hits of the most recent sweep
     std::vector<double> phi;        // [i][n]
     std::vector<RanluxSite> ranlux;  // one stream per site
+    std::vector<uint32_t> mrg;       // 6 words per site
 };
 
 static void on_coords(const orc_on* L, int64_t i, int x[4]) {
@@ -964,7 +968,8 @@ orc_on* orc_on_create(int ncomp, int nx, int ny, int nz, int nt, double kappa, d
         !(delta > 0.0) || !std::isfinite(delta))
         return nullptr;
     if (nhit < 1 || nhit > 1000) return nullptr;
-    if (rng != ORC_RNG_PHILOX && rng != ORC_RNG_CONST && rng != ORC_RNG_RANLUX) return nullptr;
+    if (rng < 0 || rng > 3) return nullptr;
+    if (rng == ORC_RNG_MRG32K3A && (seed < 1 || seed >= MRG_M2)) return nullptr;
     orc_on* L = new orc_on();
     L->n = ncomp;
     for (int m = 0; m < 4; ++m) L->d[m] = dims[m];
@@ -985,6 +990,19 @@ orc_on* orc_on_create(int ncomp, int nx, int ny, int nz, int nt, double kappa, d
         L->ranlux.resize(L->V);
         for (int64_t i = 0; i < L->V; ++i) L->ranlux[i].eng.seed(ranlux_site_seed(seed, i, lattice_id));
     }
+    if (rng == ORC_RNG_MRG32K3A) {
+        // site i's stream starts 2^127 i steps into the seed's sequence
+        L->mrg.resize(L->V * 6);
+        uint32_t st[6];
+        orc_mrg_site_state(seed, 0, st);
+        M33 j1, j2;
+        mrg_pow2(127, j1, j2);
+        for (int64_t i = 0; i < L->V; ++i) {
+            std::memcpy(&L->mrg[6 * i], st, sizeof(st));
+            m33_vec(j1, st, MRG_M1, st);
+            m33_vec(j2, st + 3, MRG_M2, st + 3);
+        }
+    }
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     for (int64_t i = 0; i < L->V; ++i) {
         double* p = &L->phi[i * ncomp];
@@ -1000,6 +1018,8 @@ orc_on* orc_on_create(int ncomp, int nx, int ny, int nz, int nt, double kappa, d
         } else if (rng == ORC_RNG_RANLUX) {
             L->ranlux[i].begin_update();
             for (int a = 0; a < ncomp; ++a) u[a] = L->ranlux[i].next();
+        } else if (rng == ORC_RNG_MRG32K3A) {
+            for (int a = 0; a < ncomp; ++a) u[a] = orc_uniform24(orc_mrg_next(&L->mrg[6 * i]));
         } else {
             for (int a = 0; a < 4; ++a) u[a] = rng_const;
         }
@@ -1040,6 +1060,9 @@ void orc_on_sweep(orc_on* L, int nsweeps) {
                     } else if (L->rng == ORC_RNG_RANLUX) {
                         for (int a = 0; a < n; ++a) u[a] = L->ranlux[i].next();
                         uacc = L->ranlux[i].next();
+                    } else if (L->rng == ORC_RNG_MRG32K3A) {
+                        for (int a = 0; a < n; ++a) u[a] = orc_uniform24(orc_mrg_next(&L->mrg[6 * i]));
+                        uacc = orc_uniform24(orc_mrg_next(&L->mrg[6 * i]));
                     } else {
                         for (int a = 0; a < 4; ++a) u[a] = L->rng_const;
                         uacc = L->rng_const;
@@ -1087,6 +1110,11 @@ void orc_on_measure(const orc_on* L, double out[7]) {
 void orc_on_get_field(const orc_on* L, double* out) { std::memcpy(out, L->phi.data(), L->phi.size() * sizeof(double)); }
 void orc_on_set_field(orc_on* L, const double* in) { std::memcpy(L->phi.data(), in, L->phi.size() * sizeof(double)); }
 uint64_t orc_on_sweeps(const orc_on* L) { return L->sweeps; }
+int orc_on_get_mrg_states(const orc_on* L, uint32_t* out) {
+    if (L->rng != ORC_RNG_MRG32K3A) return -1;
+    std::memcpy(out, L->mrg.data(), L->mrg.size() * sizeof(uint32_t));
+    return 0;
+}
 double orc_on_acceptance(const orc_on* L) {
     return (double)L->accepted_last / ((double)L->V * (double)L->nhit);
 }

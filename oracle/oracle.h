@@ -91,7 +91,7 @@ void orc_staple(const orc_lattice* L, int64_t i, int mu, double* A);
 
 /* ---- O(N) phi^4 model: N-vector per site, multi-hit Metropolis ---- */
 typedef struct orc_on orc_on;
-/* ncomp = N in 1..4; rng Philox, constant or RANLUX; nhit 1..1000;
+/* ncomp = N in 1..4; any of the four generators; nhit 1..1000;
  * lambda >= 0, delta > 0.  Returns NULL on invalid arguments.  Field layout
  * [site i][component a], FP64. */
 orc_on* orc_on_create(int ncomp, int nx, int ny, int nz, int nt, double kappa, double lambda, double h,
@@ -103,6 +103,8 @@ void orc_on_measure(const orc_on* L, double out[7]);
 void orc_on_get_field(const orc_on* L, double* out);
 void orc_on_set_field(orc_on* L, const double* in);
 uint64_t orc_on_sweeps(const orc_on* L);
+/* MRG32k3a states, 6 words per site; -1 for the other generators. */
+int orc_on_get_mrg_states(const orc_on* L, uint32_t* out);
 /* Accepted hits of the most recent sweep / (V * NHIT). */
 double orc_on_acceptance(const orc_on* L);
 

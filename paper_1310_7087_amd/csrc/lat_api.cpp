@@ -505,6 +505,11 @@ int lat_internal_fail(int code, const char* msg) {
     return code;
 }
 
+// MRG32k3a per-site stream states (canonical site order) for the O(N) fields.
+std::vector<uint32_t> lat_internal_mrg_site_states(uint64_t seed, int64_t nsites) {
+    return mrg_site_states(seed, nsites);
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================

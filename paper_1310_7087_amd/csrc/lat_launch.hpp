@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "lat_types.hpp"
 
 hipError_t lat_launch_pass(int group, int storage, int kind, bool reunit, int rng, const PassArgs& a, int block,
@@ -21,3 +23,6 @@ hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t*
                             hipStream_t st);
 // Sets the calling thread's error message (lat_last_error) and returns code.
 int lat_internal_fail(int code, const char* msg);
+// MRG32k3a states of sites 0..nsites-1 (6 words each): the seed's stream
+// (s, s, s, s, s, s) advanced by 2^127 steps per site.
+std::vector<uint32_t> lat_internal_mrg_site_states(uint64_t seed, int64_t nsites);

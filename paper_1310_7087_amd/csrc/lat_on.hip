@@ -6,8 +6,8 @@
 // Layout in HBM: the field is split by parity, then by component, into planes
 // of vp = vh rounded up to 256 values (FP64 or FP32): value a of the site with
 // half-lattice index s and parity p sits at planes[(p * N + a) * vp + s], so
-// every load of a wave is one contiguous run per component.  RANLUX states
-// use the same [parity][word][vp] planes (25 words).
+// every load of a wave is one contiguous run per component.  Generator
+// states use the same [parity][word][vp] planes (RANLUX 25 words, MRG32k3a 6).
 //
 // One thread updates one site: it reads the 2 * 4 neighbours of the other
 // parity once, keeps the neighbour sum and the site in registers, and runs
@@ -39,7 +39,7 @@ constexpr int ON_SERIES_CAP = 1024;   // measurements buffered on the device per
 struct OnArgs {
     LatGeom g;
     char* field;          // [parity][component][vp] of T
-    uint32_t* rl;         // RANLUX states [parity][word 0..24][vp], or null
+    uint32_t* rl;         // generator states [parity][word][vp] (RANLUX 25, MRG32k3a 6 words), or null
     uint32_t* acc;        // [nblocks] accepted hits of this pass's work-groups
     double kappa, lambda, h, delta, rng_const;
     uint32_t key0, key1, lat_id, sweep;
@@ -96,8 +96,12 @@ __global__ void __launch_bounds__(256) on_pass(OnArgs a) {
         }
         draws<RNG> d;
         uint32_t site = 0;
+        mrg_state ms;
         if constexpr (RNG == LAT_RNG_PHILOX_I) {
             site = (uint32_t)canon_index(a.g, c);
+        } else if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+            for (int w = 0; w < 6; ++w) ms.s[w] = a.rl[((int64_t)p * 6 + w) * vp + s];
         } else if constexpr (RNG == LAT_RNG_RANLUX_I) {
             // every site update begins a new block of the site's stream
             uint32_t b[24];
@@ -132,6 +136,10 @@ __global__ void __launch_bounds__(256) on_pass(OnArgs a) {
 #pragma unroll
                     for (int j = 0; j < N; ++j) v[j] = w[j] >> 8;
                     uacc = accept_u24(o.x, o.y, o.z);
+                } else if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+                    for (int j = 0; j < N; ++j) v[j] = mrg_step(ms) >> 8;
+                    uacc = u24(mrg_step(ms));
                 } else {
 #pragma unroll
                     for (int j = 0; j < N; ++j) v[j] = d.next();
@@ -166,6 +174,10 @@ __global__ void __launch_bounds__(256) on_pass(OnArgs a) {
 #pragma unroll
             for (int j = 0; j < 24; ++j) a.rl[((int64_t)p * 25 + j) * vp + s] = d.lds[j * d.stride];
             a.rl[((int64_t)p * 25 + 24) * vp + s] = d.c;  // a block has been delivered
+        }
+        if constexpr (RNG == LAT_RNG_MRG_I) {
+#pragma unroll
+            for (int w = 0; w < 6; ++w) a.rl[((int64_t)p * 6 + w) * vp + s] = ms.s[w];
         }
     }
     // accepted hits of the work-group: wave sums, then one store per group
@@ -205,6 +217,11 @@ __global__ void __launch_bounds__(256) on_init(OnArgs a, int hot) {
             for (int k = 0; k < N; ++k) u[k] = u24(b[k] << 8);
             for (int w = 0; w < 24; ++w) a.rl[((int64_t)p * 25 + w) * vp + s] = b[w];
             a.rl[((int64_t)p * 25 + 24) * vp + s] = cy;
+        } else if constexpr (RNG == LAT_RNG_MRG_I) {
+            mrg_state ms;
+            for (int w = 0; w < 6; ++w) ms.s[w] = a.rl[((int64_t)p * 6 + w) * vp + s];
+            for (int k = 0; k < N; ++k) u[k] = u24(mrg_step(ms));
+            for (int w = 0; w < 6; ++w) a.rl[((int64_t)p * 6 + w) * vp + s] = ms.s[w];
         } else {
             for (int k = 0; k < 4; ++k) u[k] = a.rng_const;
         }
@@ -299,19 +316,19 @@ __global__ void __launch_bounds__(256) on_convert(OnArgs a, int N, int to_dev, d
     }
 }
 
-// RANLUX states: device planes [parity][word][vp] <-> canonical [site][25]
-__global__ void __launch_bounds__(256) on_rl_convert(OnArgs a, int to_dev, uint32_t* canon) {
+// generator states: device planes [parity][word][vp] <-> canonical [site][nw]
+__global__ void __launch_bounds__(256) on_rl_convert(OnArgs a, int nw, int to_dev, uint32_t* canon) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= 2 * a.g.vh) return;
     const int p = j >= a.g.vh ? 1 : 0;
     const int64_t s = j - p * a.g.vh;
     const int64_t i = canon_index(a.g, decode(a.g, s, p));
-    for (int w = 0; w < 25; ++w) {
-        uint32_t* pl = a.rl + ((int64_t)p * 25 + w) * a.g.vh_pad;
+    for (int w = 0; w < nw; ++w) {
+        uint32_t* pl = a.rl + ((int64_t)p * nw + w) * a.g.vh_pad;
         if (to_dev)
-            pl[s] = canon[i * 25 + w];
+            pl[s] = canon[i * nw + w];
         else
-            canon[i * 25 + w] = pl[s];
+            canon[i * nw + w] = pl[s];
     }
 }
 
@@ -322,6 +339,7 @@ hipError_t launch_pass_t(int rng, const OnArgs& a, int block, hipStream_t st) {
     switch (rng) {
         case LAT_RNG_PHILOX_I: hipLaunchKernelGGL((on_pass<T, N, LAT_RNG_PHILOX_I>), grid, dim3(block), 0, st, a); break;
         case LAT_RNG_RANLUX_I: hipLaunchKernelGGL((on_pass<T, N, LAT_RNG_RANLUX_I>), grid, dim3(block), 0, st, a); break;
+        case LAT_RNG_MRG_I: hipLaunchKernelGGL((on_pass<T, N, LAT_RNG_MRG_I>), grid, dim3(block), 0, st, a); break;
         default: hipLaunchKernelGGL((on_pass<T, N, LAT_RNG_CONST_I>), grid, dim3(block), 0, st, a); break;
     }
     return hipGetLastError();
@@ -332,6 +350,7 @@ hipError_t launch_init_t(int rng, const OnArgs& a, int hot, hipStream_t st) {
     switch (rng) {
         case LAT_RNG_PHILOX_I: hipLaunchKernelGGL((on_init<T, N, LAT_RNG_PHILOX_I>), grid, dim3(256), 0, st, a, hot); break;
         case LAT_RNG_RANLUX_I: hipLaunchKernelGGL((on_init<T, N, LAT_RNG_RANLUX_I>), grid, dim3(256), 0, st, a, hot); break;
+        case LAT_RNG_MRG_I: hipLaunchKernelGGL((on_init<T, N, LAT_RNG_MRG_I>), grid, dim3(256), 0, st, a, hot); break;
         default: hipLaunchKernelGGL((on_init<T, N, LAT_RNG_CONST_I>), grid, dim3(256), 0, st, a, hot); break;
     }
     return hipGetLastError();
@@ -390,6 +409,9 @@ namespace {
 
 size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// 32-bit words of per-site generator state
+int state_words(int rng) { return rng == LAT_RNG_RANLUX ? 25 : rng == LAT_RNG_MRG32K3A ? 6 : 0; }
+
 // Parameter checks and the device layout; 0 on success.
 int on_layout(lat_on_ctx& c, int n, const int d[4], const lat_options& o) {
     if (n < 1 || n > 4) return lat_internal_fail(LAT_EINVAL, "O(N): ncomp must be 1..4");
@@ -399,8 +421,7 @@ int on_layout(lat_on_ctx& c, int n, const int d[4], const lat_options& o) {
     if (V > ((int64_t)1 << 32)) return lat_internal_fail(LAT_EINVAL, "lattice too large (V > 2^32)");
     if (o.storage != LAT_F64 && o.storage != LAT_F32)
         return lat_internal_fail(LAT_EUNSUPPORTED, "O(N) fields are stored as LAT_F64 or LAT_F32");
-    if (o.rng != LAT_RNG_PHILOX && o.rng != LAT_RNG_CONST && o.rng != LAT_RNG_RANLUX)
-        return lat_internal_fail(LAT_EUNSUPPORTED, "O(N) fields use Philox, RANLUX or the constant generator");
+    if (o.rng < LAT_RNG_MRG32K3A || o.rng > LAT_RNG_RANLUX) return lat_internal_fail(LAT_EINVAL, "unknown generator");
     if (o.rng == LAT_RNG_CONST && !(o.rng_const > 0.0 && o.rng_const < 1.0))
         return lat_internal_fail(LAT_EINVAL, "rng_const must lie in (0,1)");
     if (o.nhit < 1 || o.nhit > 1000) return lat_internal_fail(LAT_EINVAL, "O(N): nhit must be 1..1000");
@@ -425,7 +446,7 @@ int on_layout(lat_on_ctx& c, int n, const int d[4], const lat_options& o) {
     c.field_off = off;
     off = up(off + 2 * (size_t)n * c.g.vh_pad * tb, 256);
     c.rl_off = off;
-    c.rl_bytes = o.rng == LAT_RNG_RANLUX ? 2 * 25 * (size_t)c.g.vh_pad * 4 : 0;
+    c.rl_bytes = 2 * (size_t)state_words(o.rng) * c.g.vh_pad * 4;
     off = up(off + c.rl_bytes, 256);
     c.acc_off = off;
     off = up(off + 2 * (size_t)c.nb_pass * 4, 256);
@@ -457,7 +478,12 @@ OnArgs on_args(const lat_on_ctx* c, int parity) {
     return a;
 }
 
-int rng_i(int rng) { return rng == LAT_RNG_PHILOX ? LAT_RNG_PHILOX_I : rng == LAT_RNG_RANLUX ? LAT_RNG_RANLUX_I : LAT_RNG_CONST_I; }
+int rng_i(int rng) {
+    return rng == LAT_RNG_PHILOX ? LAT_RNG_PHILOX_I
+           : rng == LAT_RNG_RANLUX ? LAT_RNG_RANLUX_I
+           : rng == LAT_RNG_MRG32K3A ? LAT_RNG_MRG_I
+                                     : LAT_RNG_CONST_I;
+}
 
 hipError_t launch(const lat_on_ctx* c, int what, const OnArgs& a, int hot, double* partial) {
     if (c->storage == LAT_F64)
@@ -480,31 +506,45 @@ int enqueue_measure(lat_on_ctx* c, double* out) {
     return LAT_OK;
 }
 
-// RANLUX site states on the host, in the device's [parity][word][vp] order.
-std::vector<uint32_t> ranlux_planes(const lat_on_ctx* c) {
+// Per-site generator states on the host, canonical site order: RANLUX 25
+// words (seeded as the SU(N) streams are), MRG32k3a 6 words (streams 2^127
+// apart).
+std::vector<uint32_t> canonical_states(const lat_on_ctx* c) {
+    if (c->rng == LAT_RNG_MRG32K3A) return lat_internal_mrg_site_states(c->seed, c->V());
     const uint64_t M = 2147483561ull;
-    std::vector<uint32_t> out(2 * 25 * (size_t)c->g.vh_pad, 0u);
+    std::vector<uint32_t> out((size_t)c->V() * 25);
     for (int64_t i = 0; i < c->V(); ++i) {
-        int64_t r = i;
-        const int x = (int)(r % c->g.nx);
-        r /= c->g.nx;
-        const int y = (int)(r % c->g.ny);
-        r /= c->g.ny;
-        const int z = (int)(r % c->g.nz);
-        const int t = (int)(r / c->g.nz);
-        const int p = (x + y + z + t) & 1;
-        const int64_t s = (x >> 1) + (int64_t)c->g.nxh * (y + (int64_t)c->g.ny * (z + (int64_t)c->g.nz * t));
         const uint64_t j = ((uint64_t)i + 2654435761ull * (uint64_t)c->lat_id) % M;
         uint64_t e = 1 + ((c->seed % M) + 1000003ull * j) % M;
-        uint32_t w[25];
+        uint32_t* w = &out[(size_t)i * 25];
         for (int k = 0; k < 24; ++k) {
             e = (40014ull * e) % 2147483563ull;
             w[k] = (uint32_t)(e & 0xFFFFFFu);
         }
         w[24] = (w[23] == 0 ? 1u : 0u) | 2u;
-        for (int k = 0; k < 25; ++k) out[((size_t)p * 25 + k) * c->g.vh_pad + s] = w[k];
     }
     return out;
+}
+
+// Copies the generator states between the device planes and a host array in
+// canonical site order; synchronises.
+int rl_transfer(lat_on_ctx* c, uint32_t* host, bool to_dev) {
+    const int nw = state_words(c->rng);
+    const size_t n = (size_t)c->V() * nw;
+    uint32_t* dev = nullptr;
+    ON_TRY(hipMalloc((void**)&dev, n * 4));
+    hipError_t e = hipSuccess;
+    if (to_dev) e = hipMemcpyAsync(dev, host, n * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(on_rl_convert, dim3((unsigned)((c->V() + 255) / 256)), dim3(256), 0, c->stream,
+                           on_args(c, 0), nw, to_dev ? 1 : 0, dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !to_dev) e = hipMemcpyAsync(host, dev, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dev);
+    if (e != hipSuccess) return lat_internal_fail(LAT_EDEVICE, hip_msg("generator state transfer", e).c_str());
+    return LAT_OK;
 }
 
 void destroy(lat_on_ctx* c) {
@@ -536,34 +576,12 @@ int create_device(lat_on_ctx* c, const lat_options& o) {
         c->own_mem = true;
     }
     ON_TRY(hipMemsetAsync(c->base, 0, c->total, c->stream));
-    if (c->rng == LAT_RNG_RANLUX) {
-        std::vector<uint32_t> st = ranlux_planes(c);
-        ON_TRY(hipMemcpyAsync(c->rl(), st.data(), st.size() * 4, hipMemcpyHostToDevice, c->stream));
-        ON_TRY(launch(c, 1, on_args(c, 0), c->start == LAT_HOT, nullptr));
-        ON_TRY(hipStreamSynchronize(c->stream));  // st goes out of scope
-        return LAT_OK;
+    if (state_words(c->rng)) {
+        std::vector<uint32_t> st = canonical_states(c);
+        const int rc = rl_transfer(c, st.data(), true);
+        if (rc) return rc;
     }
     ON_TRY(launch(c, 1, on_args(c, 0), c->start == LAT_HOT, nullptr));
-    return LAT_OK;
-}
-
-// Copies the RANLUX states between the device planes and a host array in
-// canonical site order (25 words per site); synchronises.
-int rl_transfer(lat_on_ctx* c, uint32_t* host, bool to_dev) {
-    const size_t n = (size_t)c->V() * 25;
-    uint32_t* dev = nullptr;
-    ON_TRY(hipMalloc((void**)&dev, n * 4));
-    hipError_t e = hipSuccess;
-    if (to_dev) e = hipMemcpyAsync(dev, host, n * 4, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(on_rl_convert, dim3((unsigned)((c->V() + 255) / 256)), dim3(256), 0, c->stream,
-                           on_args(c, 0), to_dev ? 1 : 0, dev);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess && !to_dev) e = hipMemcpyAsync(host, dev, n * 4, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(dev);
-    if (e != hipSuccess) return lat_internal_fail(LAT_EDEVICE, hip_msg("RANLUX state transfer", e).c_str());
     return LAT_OK;
 }
 
@@ -626,11 +644,17 @@ int lat_on_create(lat_on_t* out, int ncomp, int Nx, int Ny, int Nz, int Nt, doub
     c->start = o.start;
     c->nhit = o.nhit;
     c->lat_id = o.lattice_id;
+    const uint64_t MRG_M2 = 4294944443ull;
     uint64_t seed = o.seed;
     if (seed == 0) {
         seed = (uint64_t)std::chrono::high_resolution_clock::now().time_since_epoch().count();
         seed ^= seed >> 29;
         if (!seed) seed = 1;
+        if (o.rng == LAT_RNG_MRG32K3A) seed = 1 + seed % (MRG_M2 - 1);
+    }
+    if (o.rng == LAT_RNG_MRG32K3A && seed >= MRG_M2) {
+        delete c;
+        return lat_internal_fail(LAT_EINVAL, "MRG32k3a seed must be in [1, 4294944443)");
     }
     c->seed = seed;
     rc = create_device(c, o);
@@ -779,8 +803,8 @@ int lat_on_save(lat_on_t c, const char* path) {
     int rc = lat_on_get_field(c, field.data(), field.size());
     if (rc) return rc;
     std::vector<uint32_t> words;
-    if (c->rng == LAT_RNG_RANLUX) {
-        words.resize((size_t)c->V() * 25);
+    if (state_words(c->rng)) {
+        words.resize((size_t)c->V() * state_words(c->rng));
         if ((rc = rl_transfer(c, words.data(), false))) return rc;
     }
     OnCkptHeader hd;
@@ -838,7 +862,7 @@ int lat_on_load(lat_on_t* out, const char* path, const lat_options* opt) {
     }
     const uint64_t V = (uint64_t)hd.dims[0] * hd.dims[1] * hd.dims[2] * hd.dims[3];
     if (V == 0 || V > ((uint64_t)1 << 32) || hd.n_doubles != V * hd.ncomp ||
-        hd.n_words != (hd.rng == LAT_RNG_RANLUX ? V * 25 : 0)) {
+        hd.rng > LAT_RNG_RANLUX || hd.n_words != V * (uint64_t)state_words((int)hd.rng)) {
         std::fclose(f);
         return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint sizes do not match its header");
     }

@@ -53,9 +53,10 @@ def test_start_and_sweeps_match_oracle(case):
     g.close()
 
 
+@pytest.mark.parametrize("rng", [O.RNG_RANLUX, O.RNG_MRG32K3A])
 @pytest.mark.parametrize("n", [1, 4])
-def test_ranlux_streams_match_oracle(n):
-    g, o = pair(n, (8, 4, 4, 6), 0.28, 0.9, 0.1, 1.1, O.HOT, 30, rng=O.RNG_RANLUX, seed=77)
+def test_sequential_streams_match_oracle(n, rng):
+    g, o = pair(n, (8, 4, 4, 6), 0.28, 0.9, 0.1, 1.1, O.HOT, 30, rng=rng, seed=77)
     assert np.array_equal(g.get_field(), o.get_field())
     g.sweep(2)
     o.sweep(2)
@@ -153,7 +154,7 @@ def test_full_size_o4_32():
     g.close()
 
 
-@pytest.mark.parametrize("rng", [P.RNG_PHILOX, P.RNG_RANLUX])
+@pytest.mark.parametrize("rng", [P.RNG_PHILOX, P.RNG_RANLUX, P.RNG_MRG32K3A])
 def test_checkpoint_continues_the_chain(tmp_path, rng):
     """N sweeps straight equal N/2 + save + load + N/2, bit for bit."""
     a = P.ONField(4, (6, 4, 8, 2), 0.3, 1.0, 0.1, 0.55, rng=rng, seed=8, nhit=25)
@@ -248,3 +249,12 @@ def test_wrong_buffer_sizes_are_rejected():
     assert P.lib.lat_on_get_field(f._h, ptr, buf.size) == P.EINVAL
     assert P.lib.lat_on_get_field(f._h, None, f.V * 3) == P.EINVAL
     f.close()
+
+
+def test_mrg_cold_start_and_states_match_oracle():
+    g, o = pair(3, (6, 4, 2, 4), 0.2, 0.4, 0.0, 0.9, O.COLD, 12, rng=O.RNG_MRG32K3A, seed=123)
+    g.sweep(3)
+    o.sweep(3)
+    assert np.abs(g.get_field() - o.get_field()).max() <= TOL64
+    assert g.acceptance() == o.acceptance()
+    g.close()

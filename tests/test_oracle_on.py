@@ -124,7 +124,8 @@ def test_quadrature_gaussian_limit():
 
 
 @pytest.mark.parametrize("n,lam,h,rng", [(4, 0.5, 0.3, O.RNG_PHILOX), (1, 1.0, 0.4, O.RNG_PHILOX),
-                                         (2, 0.2, 0.0, O.RNG_PHILOX), (3, 0.7, 0.5, O.RNG_RANLUX)])
+                                         (2, 0.2, 0.0, O.RNG_PHILOX), (3, 0.7, 0.5, O.RNG_RANLUX),
+                                         (4, 0.3, 0.2, O.RNG_MRG32K3A)])
 def test_decoupled_sites_sample_the_one_site_density(n, lam, h, rng):
     f = O.ONField(n, (4, 4, 4, 4), 0.0, lam, h, 1.4, rng=rng, seed=17, nhit=6, start=O.HOT)
     s = series(f, 3000, 50)
@@ -184,6 +185,29 @@ def test_ranlux_block_rule():
         assert np.array_equal(phi1[i], trial if accept else phi0[i])
 
 
+def test_mrg_stream_layout():
+    """MRG32k3a: each site draws sequentially from its own stream (2^127
+    apart): the hot start takes N values, each hit N then the acceptance
+    value; reproduced from the raw generator at kappa = lambda = h = 0."""
+    seed, n, nhit = 77, 3, 2
+    f = O.ONField(n, (2, 2, 2, 2), 0.0, 0.0, 0.0, 0.7, rng=O.RNG_MRG32K3A, seed=seed, nhit=nhit, start=O.HOT)
+    phi0 = f.get_field().copy()
+    f.sweep(1)
+    phi1 = f.get_field()
+    for i in range(16):
+        st = O.mrg_site_state(seed, i)
+        u = [O.uniform24(O.mrg_next(st)) for _ in range(n + nhit * (n + 1))]
+        cur = 2 * np.array(u[:n]) - 1
+        assert np.array_equal(phi0[i], cur)
+        for k in range(nhit):
+            r = np.array(u[n + k * (n + 1): n + k * (n + 1) + n])
+            trial = cur + 0.7 * (2 * r - 1)
+            if u[n + k * (n + 1) + n] < math.exp(-(trial @ trial - cur @ cur)):
+                cur = trial
+        assert np.allclose(phi1[i], cur, rtol=0, atol=1e-15)
+        assert np.array_equal(f.mrg_states()[i], st)
+
+
 def test_hot_start_is_uniform_in_the_cube():
     f = O.ONField(4, (8, 8, 8, 8), 0.3, 1.0, start=O.HOT, seed=3)
     phi = f.get_field()
@@ -217,4 +241,6 @@ def test_rejects_bad_parameters():
     with pytest.raises(ValueError):
         O.ONField(4, (4, 4, 4, 4), 0.1, 0.1, delta=0.0)
     with pytest.raises(ValueError):
-        O.ONField(4, (4, 4, 4, 4), 0.1, 0.1, rng=O.RNG_MRG32K3A)
+        O.ONField(4, (4, 4, 4, 4), 0.1, 0.1, rng=O.RNG_MRG32K3A, seed=0)
+    with pytest.raises(ValueError):
+        O.ONField(4, (4, 4, 4, 4), 0.1, 0.1, rng=5)
