@@ -47,6 +47,7 @@ int fail(int code, const char* fmt, ...) {
 constexpr uint64_t MRG_M1 = 4294967087ull;
 constexpr uint64_t MRG_M2 = 4294944443ull;
 constexpr int MEAS_CAPACITY = 4096;  // measurements buffered on the device per lat_run chunk
+constexpr int RUN_UNITS = 8;         // compound sweeps per graph launch in steady lat_run loops
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -224,7 +225,8 @@ struct lat_ctx {
     int8_t* accept_log = nullptr;
     size_t accept_bytes = 0;
     size_t accept_valid = 0;
-    std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // captured compound sweeps keyed by (n_hb, n_or, with measurement, repeats)
+    std::map<std::tuple<int, int, int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 
     char* links() const { return base + lay.links_off; }
     uint32_t* mrg() const { return lay.mrg_bytes ? reinterpret_cast<uint32_t*>(base + lay.mrg_off) : nullptr; }
@@ -275,6 +277,8 @@ PassArgs pass_args(const lat_ctx* h) {
     a.lds_reserve = h->lds_reserve;
     a.reverse = 0;
     a.frozen = h->frozen;
+    a.bump_counter = h->hb();
+    a.bump_by = 0;
     if (a.tile_order == 0) {
         // z-slabs per XCD need whole work-groups per z-plane and 8 | Nz
         const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
@@ -301,15 +305,23 @@ int enqueue_sweep(lat_ctx* h, int n_hb, int n_or) {
                 a.mu = mu;
                 a.parity = p;
                 a.reverse = h->alternate ? p : 0;
+                // the last pass advances the heat-bath counter if it is an
+                // overrelaxation pass (those do not read it)
+                const bool last = reunit && mu == 3 && p == 1;
+                a.bump_by = (last && kind == 1) ? n_hb : 0;
                 HIP_TRY(lat_launch_pass(h->group, h->storage, kind, reunit, h->rng, a, h->block, h->stream));
             }
     }
-    if (n_hb > 0) HIP_TRY(lat_launch_bump(h->hb(), n_hb, h->stream));
+    if (n_hb > 0 && n_or == 0) HIP_TRY(lat_launch_bump(h->hb(), n_hb, h->stream));
     return LAT_OK;
 }
 
-int get_graph(lat_ctx* h, int n_hb, int n_or, hipGraphExec_t* out) {
-    auto key = std::make_pair(n_hb, n_or);
+int enqueue_measure(lat_ctx* h, bool series);
+
+// `units` compound sweeps, each optionally followed by a measurement into the
+// next slot of the device series, captured as one graph on first use.
+int get_graph(lat_ctx* h, int n_hb, int n_or, bool measure, int units, hipGraphExec_t* out) {
+    auto key = std::make_tuple(n_hb, n_or, measure ? 1 : 0, units);
     auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         *out = it->second.second;
@@ -317,7 +329,11 @@ int get_graph(lat_ctx* h, int n_hb, int n_or, hipGraphExec_t* out) {
     }
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_sweep(h, n_hb, n_or);
+    int rc = LAT_OK;
+    for (int u = 0; u < units && rc == LAT_OK; ++u) {
+        rc = enqueue_sweep(h, n_hb, n_or);
+        if (rc == LAT_OK && measure) rc = enqueue_measure(h, true);
+    }
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (rc != LAT_OK) {
         if (graph) discard(hipGraphDestroy(graph));
@@ -351,16 +367,16 @@ int ensure_accept_log(lat_ctx* h, int n_hb) {
     return LAT_OK;
 }
 
-int do_sweep(lat_ctx* h, int n_hb, int n_or) {
-    if (n_hb + n_or == 0) return LAT_OK;
+int do_sweep(lat_ctx* h, int n_hb, int n_or, bool measure = false, int units = 1) {
+    if (n_hb + n_or == 0) return measure ? enqueue_measure(h, true) : LAT_OK;
     int rc = ensure_accept_log(h, n_hb);
     if (rc) return rc;
     hipGraphExec_t ex;
-    rc = get_graph(h, n_hb, n_or, &ex);
+    rc = get_graph(h, n_hb, n_or, measure, units, &ex);
     if (rc) return rc;
     HIP_TRY(hipGraphLaunch(ex, h->stream));
-    h->hb_sweeps += (uint64_t)n_hb;
-    h->sweeps += 1;
+    h->hb_sweeps += (uint64_t)n_hb * units;
+    h->sweeps += (uint64_t)units;
     return LAT_OK;
 }
 
@@ -652,13 +668,21 @@ int lat_run(lat_t h, int n_sweeps, int n_hb, int n_or, int measure_every, double
         HIP_TRY(hipMemcpyAsync(h->slot(), &zero, sizeof zero, hipMemcpyHostToDevice, h->stream));
         return LAT_OK;
     };
-    for (int k = 0; k < n_sweeps; ++k) {
-        int rc = do_sweep(h, n_hb, n_or);
+    // Steady runs go RUN_UNITS compound sweeps (and their measurements) per
+    // graph launch; the accept log (reset before every compound sweep) and
+    // other measurement intervals take one sweep per launch.
+    for (int k = 0; k < n_sweeps;) {
+        int units = 1;
+        if (!h->log_on && n_hb + n_or > 0 && measure_every <= 1 && n_sweeps - k >= RUN_UNITS &&
+            pending + RUN_UNITS <= MEAS_CAPACITY)
+            units = RUN_UNITS;
+        const bool measuring = measure_every > 0 && (k + units) % measure_every == 0;
+        int rc = do_sweep(h, n_hb, n_or, measuring, units);
         if (rc) return rc;
-        if (measure_every > 0 && (k + 1) % measure_every == 0) {
-            rc = enqueue_measure(h, true);
-            if (rc) return rc;
-            if (++pending == MEAS_CAPACITY) {
+        k += units;
+        if (measuring) {
+            pending += units;
+            if (pending == MEAS_CAPACITY) {
                 rc = flush();
                 if (rc) return rc;
             }

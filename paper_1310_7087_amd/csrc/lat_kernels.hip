@@ -215,10 +215,17 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
     }
 }
 
+// The last overrelaxation pass of a compound sweep also advances the
+// heat-bath counter (no pass that reads it runs before this kernel ends).
+LAT_DEV void pass_bump(const PassArgs& a) {
+    if (a.bump_by != 0 && blockIdx.x == 0 && threadIdx.x == 0) *a.bump_counter += (uint64_t)a.bump_by;
+}
+
 template <class ST, int KIND, bool REUNIT, int RNG, int MU>
 __global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
     const int64_t s = thread_site(a);
     if (s >= 0) su3_site<ST, KIND, REUNIT, RNG, MU>(a, s);
+    if constexpr (KIND == 1) pass_bump(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,6 +338,7 @@ template <class ST, int KIND, bool REUNIT, int RNG>
 __global__ void __launch_bounds__(256) su2_pass(PassArgs a) {
     const int64_t s = thread_site(a);
     if (s >= 0) su2_site<ST, KIND, REUNIT, RNG>(a, s);
+    if constexpr (KIND == 1) pass_bump(a);
 }
 
 // ---------------------------------------------------------------------------

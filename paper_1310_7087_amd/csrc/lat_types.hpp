@@ -41,6 +41,8 @@ struct PassArgs {
     int lds_reserve;       // dynamic LDS bytes reserved per work-group (caps occupancy)
     int reverse;           // z-slab order walked backwards (every other pass)
     int frozen;            // 1: spatial links at t = 0 are not updated
+    uint64_t* bump_counter = nullptr;  // heat-bath counter the pass advances ...
+    int bump_by = 0;                   // ... by this much when it is done (0: none)
 };
 
 // Initialisation of one lattice.
