@@ -582,3 +582,36 @@ def test_ranlux_state_survives_a_checkpoint(tmp_path):
     a.sweep(2, 2)
     b.sweep(2, 2)
     assert np.array_equal(a.get_links(), b.get_links())
+
+
+def test_run_series_in_graph_chunks_equals_stepwise():
+    """Steady lat_run loops launch eight compound sweeps (and their
+    measurements) per graph: the series, the links and the counters equal
+    those of single sweeps with a measurement after each."""
+    a = P.Lattice(3, (4, 4, 4, 4), 5.7, seed=12)
+    b = P.Lattice(3, (4, 4, 4, 4), 5.7, seed=12)
+    ps, ls = a.run(21, 1, 2, measure_every=1)
+    assert ps.shape == (21, 3)
+    for k in range(21):
+        b.sweep(1, 2)
+        p, l = b.measure()
+        assert np.array_equal(ps[k], p) and np.array_equal(ls[k], l), k
+    assert np.array_equal(a.get_links(), b.get_links())
+    assert a.info() == b.info()
+
+
+def test_run_series_across_the_device_buffer_refill():
+    """More measurements than the device series holds (4096): the buffer is
+    copied out and refilled mid-run without losing or repeating a value."""
+    a = P.Lattice(2, (2, 2, 2, 2), 2.3, seed=4)
+    b = P.Lattice(2, (2, 2, 2, 2), 2.3, seed=4)
+    n = 4096 + 27
+    ps, ls = a.run(n, 1, 1, measure_every=1)
+    p1, l1 = b.run(4000, 1, 1, measure_every=1)
+    p2, l2 = b.run(n - 4000, 1, 1, measure_every=1)
+    assert np.array_equal(ps, np.concatenate([p1, p2])) and np.array_equal(ls, np.concatenate([l1, l2]))
+    assert a.info() == b.info()
+    # and a run without measurements advances the chain the same way
+    c = P.Lattice(2, (2, 2, 2, 2), 2.3, seed=4)
+    c.run(n, 1, 1, measure_every=0)
+    assert np.array_equal(c.get_links(), a.get_links())
