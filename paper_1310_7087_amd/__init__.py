@@ -62,6 +62,14 @@ class Desc(ctypes.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime under the same soname as the system's
+    # (libamdhip64.so.7); a process can hold only one.  If torch is installed
+    # it is loaded first, so that the library and torch share torch's runtime
+    # (torch does not start on a runtime other than its own).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python paper_1310_7087_amd/build.py` "
