@@ -176,6 +176,21 @@ int lat_measure(lat_t h, double plaq[3], double poly[2]);
 
 /* Canonical FP64 links (see top); n_doubles must equal 4*V*ncomp. */
 int lat_get_links(lat_t h, double* host, size_t n_doubles);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture elsewhere in the process, tight serving loops, harnesses that
+ * forbid hipMalloc): the same canonical FP64 links as lat_get_links, bit for
+ * bit, without any device or host allocation.  The links pass through one
+ * fixed device array of LAT_NOALLOC_SCRATCH_BYTES per GPU, which the library
+ * holds from the first call on that GPU until the process ends, in chunks
+ * of whole sites (so every lattice size is accepted; no chunk exceeds the
+ * array).  n_doubles must equal 4*V*ncomp (LAT_EINVAL otherwise).
+ * Synchronises the handle's stream.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other threads, other handles) race
+ * and must be serialised by the caller.
+ */
+#define LAT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int lat_get_links_noalloc(lat_t h, double* host, size_t n_doubles);
 /* Replaces all links (rounded to the storage form; 12-real keeps rows 1-2). */
 int lat_set_links(lat_t h, const double* host, size_t n_doubles);
 /* Per-site generator states in canonical site order: MRG32k3a 6 words per

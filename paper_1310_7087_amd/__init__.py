@@ -24,6 +24,7 @@ COLD, HOT = 0, 1
 FROZEN_NONE, FROZEN_T0 = 0, 1
 
 STORAGE_NAMES = {F64: "f64", F32: "f32", F32_C12: "f32c12", F64_C12: "f64c12"}
+NOALLOC_SCRATCH_BYTES = 16 << 20  # LAT_NOALLOC_SCRATCH_BYTES of lat.h
 
 
 class LatError(RuntimeError):
@@ -87,6 +88,7 @@ def _load():
     L.lat_run.argtypes = [vp, i, i, i, i, vp, vp]
     L.lat_measure.argtypes = [vp, vp, vp]
     L.lat_get_links.argtypes = [vp, vp, sz]
+    L.lat_get_links_noalloc.argtypes = [vp, vp, sz]
     L.lat_set_links.argtypes = [vp, vp, sz]
     L.lat_get_rng_state.argtypes = [vp, vp, sz]
     L.lat_get_info.argtypes = [vp, P(u64), P(u64), P(u64)]
@@ -125,7 +127,7 @@ def _load():
     for name in ("lat_on_save", "lat_on_load", "lat_on_create", "lat_on_sweep", "lat_on_measure", "lat_on_run", "lat_on_acceptance",
                  "lat_on_get_field", "lat_on_set_field", "lat_on_get_info", "lat_on_profile", "lat_on_destroy"):
         getattr(L, name).restype = ctypes.c_int
-    for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_set_links",
+    for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_get_links_noalloc", "lat_set_links",
                  "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_autotune", "lat_set_accept_log", "lat_save", "lat_load",
                  "lat_destroy", "lat_philox4x32_10", "lat_batch_create", "lat_batch_run",
                  "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy", "lat_batch_configure",
@@ -244,6 +246,13 @@ class Lattice:
     def get_links(self) -> np.ndarray:
         out = np.empty((self.V, 4, ncomp(self.group)))
         _check(lib.lat_get_links(self._h, _ptr(out), out.size))
+        return out
+
+    def get_links_noalloc(self) -> np.ndarray:
+        """The same links as get_links, read through the library's fixed
+        per-GPU scratch array (no device allocation)."""
+        out = np.empty((self.V, 4, ncomp(self.group)))
+        _check(lib.lat_get_links_noalloc(self._h, _ptr(out), out.size))
         return out
 
     def set_links(self, links: np.ndarray) -> None:

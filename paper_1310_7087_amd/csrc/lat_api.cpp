@@ -707,6 +707,14 @@ int lat_get_links(lat_t h, double* host, size_t n_doubles) {
     return LAT_OK;
 }
 
+int lat_get_links_noalloc(lat_t h, double* host, size_t n_doubles) {
+    if (!h || !host) return fail(LAT_EINVAL, "NULL argument");
+    if (n_doubles != h->n_doubles()) return fail(LAT_EINVAL, "need %zu doubles, got %zu", h->n_doubles(), n_doubles);
+    const hipError_t e = lat_noalloc_get_links(h->group, h->storage, h->lay.g, h->links(), host, h->stream);
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "lat_get_links_noalloc: %s", hipGetErrorString(e));
+    return LAT_OK;
+}
+
 int lat_set_links(lat_t h, const double* host, size_t n_doubles) {
     if (!h || !host) return fail(LAT_EINVAL, "NULL argument");
     if (n_doubles != h->n_doubles()) return fail(LAT_EINVAL, "need %zu doubles, got %zu", h->n_doubles(), n_doubles);

@@ -21,6 +21,10 @@ hipError_t lat_launch_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint
 // heat-bath counters are advanced.
 hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t** counters, int grid, int block,
                             hipStream_t st);
+// Canonical FP64 links of a lattice copied to host memory through this
+// device's fixed scratch array, chunk by chunk (no allocation); synchronises.
+hipError_t lat_noalloc_get_links(int group, int storage, const LatGeom& g, const char* links, double* host,
+                                 hipStream_t st);
 // Sets the calling thread's error message (lat_last_error) and returns code.
 int lat_internal_fail(int code, const char* msg);
 // MRG32k3a states of sites 0..nsites-1 (6 words each): the seed's stream
