@@ -106,7 +106,9 @@ typedef struct {
     int tile_order;      /* work-group -> tile map: 0 = one z-slab per XCD (own
                             L2) when 8 | Nz, else identity (default); 1 = identity;
                             2 = reversed (order-independence tests);
-                            3 = one contiguous range of tiles per XCD */
+                            3 = one contiguous range of tiles per XCD;
+                            4 = with a 4-D tile only: one z-slab of tiles per
+                            XCD, tiles walked x, y, t, then z */
     int layout;          /* plane stride of the link arrays: 0 = staggered so that
                             planes do not alias in caches and channels (default),
                             1 = plain (padded to a multiple of 256 sites) */
@@ -122,6 +124,12 @@ typedef struct {
                             that the external field (Sec. 1, Sec. 3.2 "field
                             flux") can no longer be removed by a change of
                             variables; no random numbers are drawn for them */
+    int stage_lds;       /* SU(3) with a 4-D tile (see tile) whose extents divide
+                            the lattice, not RANLUX: 1 = each work-group first
+                            copies the opposite-parity U_mu links its sites read
+                            (six reads per link) into LDS and takes them from
+                            there; 0 = every link read goes through the caches
+                            (default).  Results are identical. */
 } lat_options;
 
 /* Fills *opt with the defaults listed above. */
@@ -213,18 +221,27 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
 
 /*
  * Autotuner (the paper foresees auto-tuning of launch parameters from
- * profiling, Sec. 6): times the sweep kernels with every candidate
- * work-group size (64, 128, 256), work-group order (0, 1) and occupancy cap
- * (none, 1, 2, 3 waves per SIMD) on compound sweeps (n_hb, n_or) of this
- * lattice, keeps the fastest, and restores the lattice's device state and
- * counters, so the Markov chain is unchanged (results do not depend on the
- * shape).  If the environment variable LAT_TUNE_CACHE names a file, choices
- * are read from and added to it: a JSON object mapping a key (storage,
- * group, extents, device) to the chosen shape, rewritten atomically.
- * result (optional) receives {work-group size, order, cap (-1 = none)}.
- * Synchronises.  LAT_ESTATE with the accept log on or an explicit 4-D tile.
+ * profiling, Sec. 6): heat-bath and overrelaxation passes get launch shapes
+ * of their own.  For each kind that the compound sweep (n_hb, n_or) runs,
+ * every candidate -- work-group size (64, 128, 256) x work-group order (0, 1)
+ * x occupancy cap (none, 1, 2, 3 waves per SIMD), and for SU(3) the
+ * LDS-staged 4-D tiles (8,4,4,2), (8,2,4,4), (4,2,4,4), (4,4,2,4) that
+ * divide the lattice (see stage_lds) -- is timed on sweeps of that kind from
+ * the same saved device state; the fastest is kept, and the lattice's device
+ * state and counters are restored, so the Markov chain is unchanged (results
+ * do not depend on the shape).  If the environment variable LAT_TUNE_CACHE
+ * names a file, choices are read from and added to it: a JSON object mapping
+ * a key (storage, group, extents, device) to both kinds' shapes (16 integers,
+ * as lat_get_launch_shape gives them), rewritten atomically.  result
+ * (optional) receives {work-group size, order, cap (-1 = none)} of the
+ * overrelaxation shape (of the heat-bath shape if n_or = 0).  Synchronises.
+ * LAT_ESTATE with the accept log on or an explicit 4-D tile.
  */
 int lat_autotune(lat_t h, int n_hb, int n_or, int result[3]);
+/* Launch shape of the heat-bath (kind 0) or overrelaxation (kind 1) passes:
+ * {work-group size, order, cap (-1 = none), tile x/2, y, z, t (0 = runs of
+ * consecutive sites), LDS-staged (0/1)}. */
+int lat_get_launch_shape(lat_t h, int kind, int shape[8]);
 
 /* Any output pointer may be NULL. */
 int lat_get_info(lat_t h, uint64_t* seed_used, uint64_t* hb_sweeps_done, uint64_t* sweeps_done);
@@ -261,8 +278,9 @@ int lat_philox4x32_10(const uint32_t* ctr, const uint32_t key[2], uint32_t* out,
 
 /* ------------------------------------------------------------------ */
 /* Batches: many independent lattices (a parameter scan, the paper's   */
-/* "trivial parallelisation", Sec. 5 and 6) advanced together by one   */
-/* persistent kernel launch per compound sweep.                        */
+/* "trivial parallelisation", Sec. 5 and 6) advanced together: each    */
+/* checkerboard pass of every member is one kernel launch covering all */
+/* members, and a compound sweep is replayed as one captured graph.    */
 /* ------------------------------------------------------------------ */
 typedef struct {
     int group, Nx, Ny, Nz, Nt;

@@ -51,6 +51,7 @@ class Options(ctypes.Structure):
         ("tile", ctypes.c_int * 4),
         ("max_waves_per_simd", ctypes.c_int),
         ("frozen", ctypes.c_int),
+        ("stage_lds", ctypes.c_int),
     ]
 
 
@@ -94,6 +95,7 @@ def _load():
     L.lat_get_info.argtypes = [vp, P(u64), P(u64), P(u64)]
     L.lat_profile_passes.argtypes = [vp, i, i, i, P(d), P(d)]
     L.lat_autotune.argtypes = [vp, i, i, vp]
+    L.lat_get_launch_shape.argtypes = [vp, i, vp]
     L.lat_set_accept_log.argtypes = [vp, i]
     L.lat_get_accept_log.argtypes = [vp, vp, sz]
     L.lat_get_accept_log.restype = i64
@@ -128,7 +130,7 @@ def _load():
                  "lat_on_get_field", "lat_on_set_field", "lat_on_get_info", "lat_on_profile", "lat_on_destroy"):
         getattr(L, name).restype = ctypes.c_int
     for name in ("lat_create", "lat_sweep", "lat_run", "lat_measure", "lat_get_links", "lat_get_links_noalloc", "lat_set_links",
-                 "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_autotune", "lat_set_accept_log", "lat_save", "lat_load",
+                 "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_autotune", "lat_get_launch_shape", "lat_set_accept_log", "lat_save", "lat_load",
                  "lat_destroy", "lat_philox4x32_10", "lat_batch_create", "lat_batch_run",
                  "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy", "lat_batch_configure",
                  "lat_batch_autotune"):
@@ -160,7 +162,7 @@ def default_options() -> Options:
 
 def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, nhit=10,
                  lattice_id=0, stream=None, device_buffer=None, block_size=0, tile_order=0,
-                 layout=0, tile=None, max_waves_per_simd=0, frozen=0) -> Options:
+                 layout=0, tile=None, max_waves_per_simd=0, frozen=0, stage_lds=0) -> Options:
     o = default_options()
     o.storage = storage
     o.rng = rng
@@ -174,6 +176,7 @@ def make_options(storage=F64, rng=RNG_PHILOX, rng_const=0.5, start=HOT, seed=1, 
     o.layout = layout
     o.max_waves_per_simd = max_waves_per_simd
     o.frozen = frozen
+    o.stage_lds = stage_lds
     if tile is not None:
         for k in range(4):
             o.tile[k] = int(tile[k])
@@ -284,6 +287,16 @@ class Lattice:
         r = np.zeros(3, dtype=np.int32)
         _check(lib.lat_autotune(self._h, int(n_hb), int(n_or), _ptr(r)))
         return {"block_size": int(r[0]), "tile_order": int(r[1]), "max_waves_per_simd": int(r[2])}
+
+    def launch_shapes(self) -> dict:
+        """Launch shapes of the heat-bath and overrelaxation passes."""
+        out = {}
+        for kind, name in ((0, "heat_bath"), (1, "overrelaxation")):
+            v = np.zeros(8, dtype=np.int32)
+            _check(lib.lat_get_launch_shape(self._h, kind, _ptr(v)))
+            out[name] = {"block_size": int(v[0]), "tile_order": int(v[1]), "max_waves_per_simd": int(v[2]),
+                         "tile": [int(x) for x in v[3:7]], "stage_lds": int(v[7])}
+        return out
 
     def set_accept_log(self, on=True):
         _check(lib.lat_set_accept_log(self._h, int(bool(on))))

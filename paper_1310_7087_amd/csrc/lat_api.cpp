@@ -201,6 +201,16 @@ int make_layout(int group, const int d[4], int storage, int rng, int layout, Lay
 // purpose: the handle is going away and an earlier error is already kept.
 inline void discard(hipError_t) {}
 
+// Launch shape of one kind of pass kernel.
+struct pass_shape {
+    int block = 256;       // work-group size
+    int tile_order = 0;    // work-group -> tile map (lat_options.tile_order)
+    int cap = -1;          // waves per SIMD (-1: no cap)
+    int lds_reserve = 0;   // dynamic LDS that enforces the cap
+    int tshape[4] = {0, 0, 0, 0};  // 4-D tile (x/2, y, z, t) or all 0
+    int stage_lds = 0;     // dynamic LDS bytes of the staged U_mu links (0: not staged)
+};
+
 struct lat_ctx {
     int group = 3, storage = LAT_F64, rng = LAT_RNG_PHILOX, start = LAT_HOT, nhit = 10, flux = 0;
     double beta = 0.0, rng_const = 0.5;
@@ -213,13 +223,12 @@ struct lat_ctx {
     bool own_stream = false;
     char* base = nullptr;
     bool own_mem = false;
-    int block = 256;
-    int tile_order = 0;
+    // launch shape of the heat-bath (0) and overrelaxation (1) passes
+    pass_shape shape[2];
     int meas_lds = 0;     // occupancy cap of the plaquette kernel (dynamic LDS bytes)
     int frozen = 0;       // LAT_FROZEN_T0: spatial links at t = 0 are not updated
     int alternate = 1;    // odd-parity passes walk the z-slab order backwards
-    int tshape[4] = {0, 0, 0, 0};
-    int lds_reserve = 0;  // caps the waves per SIMD of the pass kernels
+    bool explicit_tile = false;  // a 4-D tile was requested in the options (the tuner leaves it)
     uint64_t hb_sweeps = 0, sweeps = 0;
     bool log_on = false;
     int8_t* accept_log = nullptr;
@@ -248,7 +257,8 @@ void drop_graphs(lat_ctx* h) {
     h->graphs.clear();
 }
 
-PassArgs pass_args(const lat_ctx* h) {
+PassArgs pass_args(const lat_ctx* h, int kind) {
+    const pass_shape& sh = h->shape[kind];
     PassArgs a;
     a.g = h->lay.g;
     a.links = h->links();
@@ -265,16 +275,17 @@ PassArgs pass_args(const lat_ctx* h) {
     a.mu = 0;
     a.parity = 0;
     a.hb_offset = 0;
-    a.tile_order = h->tile_order;
+    a.tile_order = sh.tile_order;
     a.flux = h->flux;
     const int ext[4] = {h->lay.g.nxh, h->lay.g.ny, h->lay.g.nz, h->lay.g.nt};
     for (int k = 0; k < 4; ++k) {
-        a.tshape[k] = h->tshape[k];
-        a.tcount[k] = h->tshape[0] ? (ext[k] + h->tshape[k] - 1) / h->tshape[k] : 1;
+        a.tshape[k] = sh.tshape[k];
+        a.tcount[k] = sh.tshape[0] ? (ext[k] + sh.tshape[k] - 1) / sh.tshape[k] : 1;
     }
     a.nyb = 1;
     a.zslab = 1;
-    a.lds_reserve = h->lds_reserve;
+    a.lds_reserve = sh.lds_reserve;
+    a.stage_lds = sh.stage_lds;
     a.reverse = 0;
     a.frozen = h->frozen;
     a.bump_counter = h->hb();
@@ -282,8 +293,8 @@ PassArgs pass_args(const lat_ctx* h) {
     if (a.tile_order == 0) {
         // z-slabs per XCD need whole work-groups per z-plane and 8 | Nz
         const int64_t plane = (int64_t)h->lay.g.nxh * h->lay.g.ny;
-        if (!h->tshape[0] && plane % h->block == 0 && h->lay.g.nz % 8 == 0) {
-            a.nyb = (int)(plane / h->block);
+        if (!sh.tshape[0] && plane % sh.block == 0 && h->lay.g.nz % 8 == 0) {
+            a.nyb = (int)(plane / sh.block);
             a.zslab = h->lay.g.nz / 8;
         } else {
             a.tile_order = 1;
@@ -295,10 +306,11 @@ PassArgs pass_args(const lat_ctx* h) {
 // Queue one compound sweep on the handle's stream.
 int enqueue_sweep(lat_ctx* h, int n_hb, int n_or) {
     const int total = n_hb + n_or;
-    PassArgs a = pass_args(h);
+    PassArgs args[2] = {pass_args(h, 0), pass_args(h, 1)};
     for (int s = 0; s < total; ++s) {
         const int kind = s < n_hb ? 0 : 1;
         const bool reunit = (s == total - 1);
+        PassArgs& a = args[kind];
         a.hb_offset = kind == 0 ? s : 0;
         for (int mu = 0; mu < 4; ++mu)
             for (int p = 0; p < 2; ++p) {
@@ -309,7 +321,8 @@ int enqueue_sweep(lat_ctx* h, int n_hb, int n_or) {
                 // overrelaxation pass (those do not read it)
                 const bool last = reunit && mu == 3 && p == 1;
                 a.bump_by = (last && kind == 1) ? n_hb : 0;
-                HIP_TRY(lat_launch_pass(h->group, h->storage, kind, reunit, h->rng, a, h->block, h->stream));
+                HIP_TRY(lat_launch_pass(h->group, h->storage, kind, reunit, h->rng, a, h->shape[kind].block,
+                                        h->stream));
             }
     }
     if (n_hb > 0 && n_or == 0) HIP_TRY(lat_launch_bump(h->hb(), n_hb, h->stream));
@@ -416,6 +429,35 @@ int occupancy_lds(int cap, int block) {
     return lds;
 }
 
+int max_lds_per_block() {
+    int dev = 0, per_block = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return per_block;
+}
+
+bool tile_divides(const int tile[4], const int ext[4]) {
+    for (int k = 0; k < 4; ++k)
+        if (tile[k] < 1 || ext[k] % tile[k] != 0) return false;
+    return true;
+}
+
+// LDS bytes of the staged U_mu links of a tile: the box (widened by a
+// half-site on both x sides unless mu = x) plus two faces in every other
+// direction, for the direction that needs most.
+int staged_lds_bytes(int group, int storage, const int tile[4]) {
+    const int vol = tile[0] * tile[1] * tile[2] * tile[3];
+    int most = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        int n = (tile[0] + (mu ? 2 : 0)) * tile[1] * tile[2] * tile[3];
+        for (int nu = 1; nu < 4; ++nu)
+            if (nu != mu) n += 2 * vol / tile[nu];
+        most = n > most ? n : most;
+    }
+    return most * (int)bytes_per_link(group, storage);
+}
+
 uint64_t time_seed() {
     uint64_t t = (uint64_t)std::chrono::high_resolution_clock::now().time_since_epoch().count();
     t ^= t >> 29;
@@ -487,7 +529,8 @@ int check_opts(const lat_options* o) {
     if (o->nhit < 1 || o->nhit > 127) return fail(LAT_EINVAL, "nhit must be in 1..127");
     if (o->block_size != 0 && o->block_size != 64 && o->block_size != 128 && o->block_size != 256)
         return fail(LAT_EINVAL, "block_size must be 0, 64, 128 or 256");
-    if (o->tile_order < 0 || o->tile_order > 3) return fail(LAT_EINVAL, "tile_order must be 0..3");
+    if (o->tile_order < 0 || o->tile_order > 4) return fail(LAT_EINVAL, "tile_order must be 0..4");
+    if (o->tile_order == 4 && !o->tile[0]) return fail(LAT_EINVAL, "tile_order 4 needs a 4-D tile");
     if (o->layout < 0 || o->layout > 1) return fail(LAT_EINVAL, "layout must be 0 or 1");
     if (o->max_waves_per_simd < -1 || o->max_waves_per_simd > 8) return fail(LAT_EINVAL, "max_waves_per_simd -1..8");
     if (o->frozen != LAT_FROZEN_NONE && o->frozen != LAT_FROZEN_T0) return fail(LAT_EINVAL, "unknown frozen %d", o->frozen);
@@ -579,15 +622,33 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     h->frozen = o.frozen;
     h->beta = beta;
     h->lat_id = o.lattice_id;
-    h->block = o.block_size ? o.block_size : 256;
-    h->tile_order = o.tile_order;
-    int cap = o.max_waves_per_simd;
-    if (cap == 0) cap = (group == 3 && (o.storage == LAT_F64 || o.storage == LAT_F64_C12)) ? 1 : -1;
-    h->lds_reserve = cap > 0 ? -cap : 0;  // resolved once the work-group size is known
+    pass_shape sh;
+    sh.block = o.block_size ? o.block_size : 256;
+    sh.tile_order = o.tile_order;
+    sh.cap = o.max_waves_per_simd;
+    if (sh.cap == 0) sh.cap = (group == 3 && (o.storage == LAT_F64 || o.storage == LAT_F64_C12)) ? 1 : -1;
     if (o.tile[0]) {
-        for (int k = 0; k < 4; ++k) h->tshape[k] = o.tile[k];
-        h->block = o.tile[0] * o.tile[1] * o.tile[2] * o.tile[3];
+        for (int k = 0; k < 4; ++k) sh.tshape[k] = o.tile[k];
+        sh.block = o.tile[0] * o.tile[1] * o.tile[2] * o.tile[3];
+        h->explicit_tile = true;
     }
+    if (o.stage_lds) {
+        const int ext[4] = {Nx / 2, Ny, Nz, Nt};
+        if (!(o.tile[0] && group == 3 && o.rng != LAT_RNG_RANLUX && tile_divides(o.tile, ext))) {
+            delete h;
+            return fail(LAT_EINVAL, "stage_lds needs SU(3), a generator other than RANLUX and a 4-D tile "
+                                    "whose extents divide (Nx/2, Ny, Nz, Nt)");
+        }
+        const int need = staged_lds_bytes(group, o.storage, o.tile);
+        if (need > max_lds_per_block()) {
+            delete h;
+            return fail(LAT_EINVAL, "stage_lds: the tile needs %d bytes of LDS, more than a work-group has (%d)",
+                        need, max_lds_per_block());
+        }
+        sh.stage_lds = need;
+        sh.cap = -1;  // the staged links set the occupancy
+    }
+    h->shape[0] = h->shape[1] = sh;
     h->dims[0] = Nx;
     h->dims[1] = Ny;
     h->dims[2] = Nz;
@@ -607,7 +668,7 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
         return fail(LAT_EINVAL, "MRG32k3a seed must be in [1, 4294944443)");
     }
     h->seed = seed;
-    if (h->lds_reserve < 0) h->lds_reserve = occupancy_lds(-h->lds_reserve, h->block);
+    for (pass_shape& k : h->shape) k.lds_reserve = k.cap > 0 ? occupancy_lds(k.cap, k.block) : 0;
     // FP64 plaquettes run best at one wave per SIMD (less L2 thrashing), the
     // FP32 forms at full occupancy
     if (group == 3 && (o.storage == LAT_F64 || o.storage == LAT_F64_C12)) h->meas_lds = occupancy_lds(1, 256);
@@ -760,20 +821,21 @@ int lat_profile_passes(lat_t h, int n_hb, int n_or, int reps, double* ms_hb, dou
     // back to back between them
     std::vector<hipEvent_t> ev((size_t)3 * reps);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    PassArgs a = pass_args(h);
+    PassArgs args[2] = {pass_args(h, 0), pass_args(h, 1)};
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(hipEventRecord(ev[3 * r], h->stream));
         for (int s = 0; s < total; ++s) {
             const int kind = s < n_hb ? 0 : 1;
             if (s == n_hb) HIP_TRY(hipEventRecord(ev[3 * r + 1], h->stream));
+            PassArgs& a = args[kind];
             a.hb_offset = kind == 0 ? s : 0;
             for (int mu = 0; mu < 4; ++mu)
                 for (int p = 0; p < 2; ++p) {
                     a.mu = mu;
                     a.parity = p;
                     a.reverse = h->alternate ? p : 0;  // as in the captured sweep
-                    HIP_TRY(lat_launch_pass(h->group, h->storage, kind, s == total - 1, h->rng, a, h->block,
-                                            h->stream));
+                    HIP_TRY(lat_launch_pass(h->group, h->storage, kind, s == total - 1, h->rng, a,
+                                            h->shape[kind].block, h->stream));
                 }
         }
         if (n_or == 0) HIP_TRY(hipEventRecord(ev[3 * r + 1], h->stream));
@@ -892,14 +954,31 @@ void tune_cache_put(const std::string& key, const std::vector<int>& val) {
     if (ok) std::rename(tmp.c_str(), path);
 }
 
-// Time `reps` compound sweeps of the current launch shape.  Every trial
-// starts from the saved device state `backup`, so that all candidate shapes
-// are timed on the same links (the heat bath's cost depends on them); the
-// first trial also captures the shape's graph.  The faster of two trials.
+// Owners that release a device buffer or an event on every way out of a
+// scope (errors included).
+struct device_buffer_guard {
+    char* p = nullptr;
+    ~device_buffer_guard() {
+        if (p) discard(hipFree(p));
+    }
+};
+struct event_guard {
+    hipEvent_t e = nullptr;
+    ~event_guard() {
+        if (e) discard(hipEventDestroy(e));
+    }
+};
+
+// Time `reps` compound sweeps of the current launch shape, launched
+// directly on the stream.  Every trial starts from the saved device state
+// `backup`, so that all candidate shapes are timed on the same links (the
+// heat bath's cost depends on them); the first trial only warms up (code
+// objects, caches).  The faster of the two timed trials.
 int time_compound(lat_ctx* h, const char* backup, int n_hb, int n_or, int reps, double* ms) {
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    event_guard g0, g1;
+    HIP_TRY(hipEventCreate(&g0.e));
+    HIP_TRY(hipEventCreate(&g1.e));
+    const hipEvent_t e0 = g0.e, e1 = g1.e;
     int rc = LAT_OK;
     double best = 1e30;
     for (int trial = 0; trial < 3 && !rc; ++trial) {
@@ -920,11 +999,75 @@ int time_compound(lat_ctx* h, const char* backup, int n_hb, int n_or, int reps, 
         if (!rc && e != hipSuccess) rc = fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
         if (!rc && t / reps < best) best = t / reps;
     }
-    discard(hipEventDestroy(e0));
-    discard(hipEventDestroy(e1));
     if (rc) return rc;
     *ms = best;
     return LAT_OK;
+}
+
+// Candidate launch shapes of a pass kernel: work-group size x work-group
+// order x occupancy cap, and for SU(3) the LDS-staged 4-D tiles that divide
+// the lattice and fit the LDS of a work-group.
+std::vector<pass_shape> shape_candidates(const lat_ctx* h) {
+    std::vector<pass_shape> out;
+    const int blocks[3] = {64, 128, 256};
+    const int caps[4] = {-1, 1, 2, 3};
+    for (int block : blocks)
+        for (int order = 0; order < 2; ++order)
+            for (int cap : caps) {
+                pass_shape s;
+                s.block = block;
+                s.tile_order = order;
+                s.cap = cap;
+                s.lds_reserve = cap > 0 ? occupancy_lds(cap, block) : 0;
+                if (cap > 0 && s.lds_reserve == 0) continue;
+                out.push_back(s);
+            }
+    if (h->group == 3 && h->rng != LAT_RNG_RANLUX) {
+        const int tiles[4][4] = {{8, 4, 4, 2}, {8, 2, 4, 4}, {4, 2, 4, 4}, {4, 4, 2, 4}};
+        const int ext[4] = {h->lay.g.nxh, h->lay.g.ny, h->lay.g.nz, h->lay.g.nt};
+        for (const auto& t : tiles) {
+            if (!tile_divides(t, ext)) continue;
+            const int bytes = staged_lds_bytes(h->group, h->storage, t);
+            if (bytes > max_lds_per_block()) continue;
+            pass_shape s;
+            s.block = t[0] * t[1] * t[2] * t[3];
+            s.tile_order = 4;
+            for (int k = 0; k < 4; ++k) s.tshape[k] = t[k];
+            s.stage_lds = bytes;
+            out.push_back(s);
+        }
+    }
+    return out;
+}
+
+void shape_encode(const pass_shape& s, std::vector<int>& v) {
+    v.insert(v.end(), {s.block, s.tile_order, s.cap, s.tshape[0], s.tshape[1], s.tshape[2], s.tshape[3],
+                       s.stage_lds ? 1 : 0});
+}
+
+bool shape_decode(const lat_ctx* h, const int* v, pass_shape& s) {
+    s = pass_shape();
+    s.block = v[0];
+    s.tile_order = v[1];
+    s.cap = v[2];
+    for (int k = 0; k < 4; ++k) s.tshape[k] = v[3 + k];
+    const int ext[4] = {h->lay.g.nxh, h->lay.g.ny, h->lay.g.nz, h->lay.g.nt};
+    if (s.block != 64 && s.block != 128 && s.block != 256) return false;
+    if (s.tile_order < 0 || s.tile_order > 4) return false;
+    if (s.tshape[0]) {
+        if (!tile_divides(s.tshape, ext) || s.tshape[0] * s.tshape[1] * s.tshape[2] * s.tshape[3] != s.block)
+            return false;
+    } else if (s.tile_order == 4) {
+        return false;
+    }
+    if (v[7]) {
+        if (!s.tshape[0] || h->group != 3 || h->rng == LAT_RNG_RANLUX) return false;
+        s.stage_lds = staged_lds_bytes(h->group, h->storage, s.tshape);
+        if (s.stage_lds > max_lds_per_block()) return false;
+    }
+    s.lds_reserve = s.cap > 0 ? occupancy_lds(s.cap, s.block) : 0;
+    if (s.cap > 0 && s.lds_reserve == 0) return false;
+    return true;
 }
 
 }  // namespace
@@ -933,60 +1076,72 @@ extern "C" int lat_autotune(lat_t h, int n_hb, int n_or, int result[3]) {
     if (!h) return fail(LAT_EINVAL, "NULL handle");
     if (n_hb < 0 || n_or < 0 || n_hb + n_or == 0) return fail(LAT_EINVAL, "bad sweep counts");
     if (h->log_on) return fail(LAT_ESTATE, "switch the accept log off before tuning");
-    if (h->tshape[0]) return fail(LAT_ESTATE, "a 4-D work-group tile was requested explicitly");
-    const std::string key = tune_key("pass", {h->group, h->dims[0], h->dims[1], h->dims[2], h->dims[3]},
+    if (h->explicit_tile) return fail(LAT_ESTATE, "a 4-D work-group tile was requested explicitly");
+    const std::string key = tune_key("passkinds", {h->group, h->dims[0], h->dims[1], h->dims[2], h->dims[3]},
                                      h->storage);
-    std::vector<int> best;
-    if (!tune_cache_get(key, best)) {
-        // save the whole device state (links, generator states, counters)
-        char* backup = nullptr;
-        HIP_TRY(hipMalloc(&backup, h->lay.total));
+    std::vector<int> cached;
+    pass_shape tuned[2] = {h->shape[0], h->shape[1]};
+    if (tune_cache_get(key, cached) && cached.size() == 16 && shape_decode(h, cached.data(), tuned[0]) &&
+        shape_decode(h, cached.data() + 8, tuned[1])) {
+        h->shape[0] = tuned[0];
+        h->shape[1] = tuned[1];
+    } else {
+        // save the whole device state (links, generator states, counters);
+        // every candidate of a kind is timed on sweeps of that kind alone,
+        // each from the same saved state
+        device_buffer_guard backup_owner;
+        HIP_TRY(hipMalloc(&backup_owner.p, h->lay.total));
+        char* const backup = backup_owner.p;
         HIP_TRY(hipMemcpyAsync(backup, h->base, h->lay.total, hipMemcpyDeviceToDevice, h->stream));
         const uint64_t hb0 = h->hb_sweeps, sw0 = h->sweeps;
-        const int keep_block = h->block, keep_order = h->tile_order, keep_lds = h->lds_reserve;
-        double best_ms = 1e30;
+        const pass_shape keep[2] = {h->shape[0], h->shape[1]};
+        const std::vector<pass_shape> cands = shape_candidates(h);
         int rc = LAT_OK;
-        const int blocks[3] = {64, 128, 256};
-        const int caps[4] = {-1, 1, 2, 3};
-        for (int bi = 0; bi < 3 && !rc; ++bi)
-            for (int order = 0; order < 2 && !rc; ++order)
-                for (int ci = 0; ci < 4 && !rc; ++ci) {
-                    const int lds = caps[ci] > 0 ? occupancy_lds(caps[ci], blocks[bi]) : 0;
-                    if (caps[ci] > 0 && lds == 0) continue;
-                    h->block = blocks[bi];
-                    h->tile_order = order;
-                    h->lds_reserve = lds;
-                    double ms = 0.0;
-                    rc = time_compound(h, backup, n_hb, n_or, 2, &ms);
-                    if (!rc && ms < best_ms) {
-                        best_ms = ms;
-                        best = {blocks[bi], order, caps[ci]};
-                    }
+        for (int kind = 0; kind < 2 && !rc; ++kind) {
+            if ((kind == 0 ? n_hb : n_or) == 0) continue;  // this kind is not run: keep its shape
+            double best_ms = 1e30;
+            for (size_t i = 0; i < cands.size() && !rc; ++i) {
+                h->shape[kind] = cands[i];
+                double ms = 0.0;
+                rc = time_compound(h, backup, kind == 0 ? 1 : 0, kind == 1 ? 1 : 0, 2, &ms);
+                if (!rc && ms < best_ms) {
+                    best_ms = ms;
+                    tuned[kind] = cands[i];
                 }
+            }
+            h->shape[kind] = tuned[kind];
+        }
         hipError_t e = hipMemcpyAsync(h->base, backup, h->lay.total, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        discard(hipFree(backup));
         h->hb_sweeps = hb0;
         h->sweeps = sw0;
-        if (rc || e != hipSuccess || best.empty()) {
-            h->block = keep_block;
-            h->tile_order = keep_order;
-            h->lds_reserve = keep_lds;
+        if (rc || e != hipSuccess) {
+            h->shape[0] = keep[0];
+            h->shape[1] = keep[1];
             if (rc) return rc;
-            if (e != hipSuccess) return fail(LAT_EDEVICE, "autotune restore: %s", hipGetErrorString(e));
-            return fail(LAT_EDEVICE, "autotune found no runnable shape");
+            return fail(LAT_EDEVICE, "autotune restore: %s", hipGetErrorString(e));
         }
-        tune_cache_put(key, best);
+        std::vector<int> val;
+        shape_encode(h->shape[0], val);
+        shape_encode(h->shape[1], val);
+        tune_cache_put(key, val);
     }
-    h->block = best[0];
-    h->tile_order = best[1];
-    h->lds_reserve = best[2] > 0 ? occupancy_lds(best[2], best[0]) : 0;
     drop_graphs(h);
     if (result) {
-        result[0] = best[0];
-        result[1] = best[1];
-        result[2] = best[2];
+        const pass_shape& r = h->shape[n_or > 0 ? 1 : 0];
+        result[0] = r.block;
+        result[1] = r.tile_order;
+        result[2] = r.cap;
     }
+    return LAT_OK;
+}
+
+extern "C" int lat_get_launch_shape(lat_t h, int kind, int shape[8]) {
+    if (!h || !shape) return fail(LAT_EINVAL, "NULL argument");
+    if (kind != 0 && kind != 1) return fail(LAT_EINVAL, "kind must be 0 (heat bath) or 1 (overrelaxation)");
+    std::vector<int> v;
+    shape_encode(h->shape[kind], v);
+    for (int k = 0; k < 8; ++k) shape[k] = v[k];
     return LAT_OK;
 }
 

@@ -552,6 +552,7 @@ LAT_DEV void st_plane(char* base, int64_t plane_bytes, int k, uint32_t off, V v)
 }
 
 struct st_f64 {  // SU(3), 18 doubles: 9 planes of (re, im)
+    using vec = double2;  // one plane element
     using real = double;
     using mat = m3<double>;
     static constexpr int NP = 9;
@@ -575,6 +576,7 @@ struct st_f64 {  // SU(3), 18 doubles: 9 planes of (re, im)
     }
 };
 struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
+    using vec = float2;  // one plane element
     using real = float;
     using mat = m3<float>;
     static constexpr int NP = 9;
@@ -598,6 +600,7 @@ struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
     }
 };
 struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
+    using vec = float4;  // one plane element
     using real = float;
     using mat = m3<float>;
     static constexpr int NP = 3;
@@ -627,6 +630,7 @@ struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
     }
 };
 struct st_f64c12 {  // SU(3), rows 1-2 as 6 planes of (re, im) doubles; row 3 rebuilt
+    using vec = double2;  // one plane element
     using real = double;
     using mat = m3<double>;
     static constexpr int NP = 6;
@@ -651,6 +655,7 @@ struct st_f64c12 {  // SU(3), rows 1-2 as 6 planes of (re, im) doubles; row 3 re
     }
 };
 struct sq_f64 {  // SU(2), 4 doubles: 2 planes of double2
+    using vec = double2;  // one plane element
     using real = double;
     using mat = qt<double>;
     static constexpr int NP = 2;
@@ -669,6 +674,7 @@ struct sq_f64 {  // SU(2), 4 doubles: 2 planes of double2
     }
 };
 struct sq_f32 {  // SU(2), 4 floats: 1 plane of float4
+    using vec = float4;  // one plane element
     using real = float;
     using mat = qt<float>;
     static constexpr int NP = 1;

@@ -9,6 +9,8 @@
 // XCD (own L2) sweeps a contiguous slab of the lattice.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lat_dev.hpp"
 #include "lat_launch.hpp"
 
@@ -23,7 +25,8 @@ namespace {
 // every t, so neighbours in x, y and t stay in its L2 and z crosses only at
 // the slab faces (the host falls back to order 1 when 8 does not divide Nz
 // or work-groups do not tile whole z-planes); 1: identity; 2: reversed;
-// 3: one contiguous range of tiles per XCD.
+// 3: one contiguous range of tiles per XCD; 4 (4-D tiles only, see
+// thread_site): one z-slab of tiles per XCD.
 LAT_DEV int64_t tile_index(int order, int nyb = 1, int zslab = 1, int nz = 1, int reverse = 0) {
     const int64_t nb = gridDim.x, b = blockIdx.x;
     if (order == 1) return b;
@@ -50,18 +53,38 @@ LAT_DEV int64_t tile_index(int order, int nyb = 1, int zslab = 1, int nz = 1, in
 // (x/2, y, z, t) per work-group so that neighbour links are shared inside
 // the work-group and its XCD.
 LAT_DEV int64_t thread_site(const PassArgs& a) {
-    const int64_t tile = tile_index(a.tile_order, a.nyb, a.zslab, a.g.nz, a.reverse);
-    if (a.tshape[0] == 0) {
-        const int64_t s = tile * (int64_t)blockDim.x + threadIdx.x;
-        return s < a.g.vh ? s : -1;
+    int bx, by, bz, bt;
+    if (a.tshape[0] && a.tile_order == 4) {
+        // XCD-blocked 4-D tiles: the tile grid is enumerated x, y, t, then z
+        // (slowest), and XCD k (block b runs on XCD b mod 8) takes the k-th
+        // contiguous eighth of that list, i.e. a z-slab of tiles, walked in
+        // the same order (backwards on every other pass)
+        const int64_t nb = gridDim.x, b = blockIdx.x;
+        const int64_t k = b & 7, per = nb >> 3, rem = nb & 7;
+        int64_t j = b >> 3;
+        const int64_t mine = per + (k < rem ? 1 : 0);
+        if (a.reverse) j = mine - 1 - j;
+        int64_t r = k * per + (k < rem ? k : rem) + j;
+        bx = (int)(r % a.tcount[0]);
+        r /= a.tcount[0];
+        by = (int)(r % a.tcount[1]);
+        r /= a.tcount[1];
+        bt = (int)(r % a.tcount[3]);
+        bz = (int)(r / a.tcount[3]);
+    } else {
+        const int64_t tile = tile_index(a.tile_order, a.nyb, a.zslab, a.g.nz, a.reverse);
+        if (a.tshape[0] == 0) {
+            const int64_t s = tile * (int64_t)blockDim.x + threadIdx.x;
+            return s < a.g.vh ? s : -1;
+        }
+        int64_t r = tile;
+        bx = (int)(r % a.tcount[0]);
+        r /= a.tcount[0];
+        by = (int)(r % a.tcount[1]);
+        r /= a.tcount[1];
+        bz = (int)(r % a.tcount[2]);
+        bt = (int)(r / a.tcount[2]);
     }
-    int64_t r = tile;
-    const int bx = (int)(r % a.tcount[0]);
-    r /= a.tcount[0];
-    const int by = (int)(r % a.tcount[1]);
-    r /= a.tcount[1];
-    const int bz = (int)(r % a.tcount[2]);
-    const int bt = (int)(r / a.tcount[2]);
     int i = threadIdx.x;
     const int ix = i % a.tshape[0];
     i /= a.tshape[0];
@@ -85,8 +108,147 @@ constexpr int SUB_B[3] = {1, 2, 2};
 // MU >= 0 fixes the direction at compile time (the staple then is one
 // straight-line block the scheduler can interleave); MU = -1 reads it from
 // the arguments.
-template <class ST, int KIND, bool REUNIT, int RNG, int MU = -1>
-LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
+// ---------------------------------------------------------------------------
+// LDS staging of the opposite-parity U_mu links of a 4-D tile
+// ---------------------------------------------------------------------------
+// A pass reads each link U_mu(y) of the other parity six times (from the
+// sites y -+ nu, nu != mu), and those readers are spread over the whole
+// staple loop of many work-groups, longer than the per-XCD L2 keeps the
+// lines.  With staging, a work-group covers a 4-D tile of the pass parity
+// whose extents divide the lattice; it first copies into LDS every U_mu link
+// of the other parity that its sites read -- the tile's own box (in x
+// widened by one half-site on each side unless mu = x) and one face on each
+// side in every other direction nu != mu, x, with periodic wrap-around --
+// and then takes those six neighbours from LDS.  Element k of slot j sits at
+// lds + (k * nslots + j) * VB, so a wave's reads of consecutive slots are
+// contiguous.
+struct lq_tile {
+    int x0, y0, z0, t0;  // origin (x/2, y, z, t)
+    int tx, ty, tz, tt;  // extents
+    int ex;              // 1 unless mu = x: the box reaches one half-site further on both x sides
+    int nI;              // slots of the box
+    int fo[4];           // first slot of the two faces of direction nu (nu = y, z, t; nu != mu)
+    int fs[4];           // slots of one face
+    int nslots;
+};
+
+LAT_DEV lq_tile lq_make(int mu, int bx, int by, int bz, int bt, const int (&sh)[4]) {
+    lq_tile T;
+    T.tx = sh[0];
+    T.ty = sh[1];
+    T.tz = sh[2];
+    T.tt = sh[3];
+    T.x0 = bx * T.tx;
+    T.y0 = by * T.ty;
+    T.z0 = bz * T.tz;
+    T.t0 = bt * T.tt;
+    T.ex = mu == 0 ? 0 : 1;
+    T.nI = (T.tx + 2 * T.ex) * T.ty * T.tz * T.tt;
+    const int vol = T.tx * T.ty * T.tz * T.tt;
+    int off = T.nI;
+    T.fo[0] = T.fs[0] = 0;
+#pragma unroll
+    for (int nu = 1; nu < 4; ++nu) {
+        const int ext = nu == 1 ? T.ty : nu == 2 ? T.tz : T.tt;
+        T.fs[nu] = vol / ext;
+        T.fo[nu] = off;
+        if (nu != mu) off += 2 * T.fs[nu];
+    }
+    T.nslots = off;
+    return T;
+}
+
+LAT_DEV int lq_box(const lq_tile& T, int lxx, int ly, int lz, int lt) {
+    return (lxx + T.ex) + (T.tx + 2 * T.ex) * (ly + T.ty * (lz + T.tz * lt));
+}
+
+// Slot of U_mu(x + d nu) for the tile-local site (lx, ly, lz, lt) of the pass
+// parity; r = the x offset of that site within its pair of x (its row parity).
+LAT_DEV int lq_slot(const lq_tile& T, int nu, int d, int lx, int ly, int lz, int lt, int r) {
+    switch (nu) {
+        case 0: return lq_box(T, lx + (d > 0 ? r : r - 1), ly, lz, lt);
+        case 1: {
+            const int l = ly + d;
+            if (l >= 0 && l < T.ty) return lq_box(T, lx, l, lz, lt);
+            return T.fo[1] + (l < 0 ? 0 : T.fs[1]) + lx + T.tx * (lz + T.tz * lt);
+        }
+        case 2: {
+            const int l = lz + d;
+            if (l >= 0 && l < T.tz) return lq_box(T, lx, ly, l, lt);
+            return T.fo[2] + (l < 0 ? 0 : T.fs[2]) + lx + T.tx * (ly + T.ty * lt);
+        }
+        default: {
+            const int l = lt + d;
+            if (l >= 0 && l < T.tt) return lq_box(T, lx, ly, lz, l);
+            return T.fo[3] + (l < 0 ? 0 : T.fs[3]) + lx + T.tx * (ly + T.ty * lz);
+        }
+    }
+}
+
+LAT_DEV int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// Copies the tile's U_mu links of parity q into LDS (all threads of the
+// work-group; the caller synchronises).
+template <class ST>
+LAT_DEV void lq_fill(const PassArgs& a, const lq_tile& T, int mu, int q, char* lds) {
+    using V = typename ST::vec;
+    const char* src = dir_base<ST>(a.links, a.g.vh_pad, q, mu);
+    const int64_t pb = a.g.vh_pad * ST::VB;
+    for (int j = threadIdx.x; j < T.nslots; j += blockDim.x) {
+        int xh, y, z, t;
+        if (j < T.nI) {
+            const int w = T.tx + 2 * T.ex;
+            int r = j / w;
+            xh = T.x0 + (j - r * w) - T.ex;
+            y = T.y0 + r % T.ty;
+            r /= T.ty;
+            z = T.z0 + r % T.tz;
+            t = T.t0 + r / T.tz;
+        } else {
+            int nu = 1;
+            while (nu < 3 && (nu == mu || j >= T.fo[nu] + 2 * T.fs[nu])) ++nu;
+            const int k = j - T.fo[nu];
+            const int side = k >= T.fs[nu];
+            const int i = side ? k - T.fs[nu] : k;
+            const int lx = i % T.tx;
+            const int rest = i / T.tx;
+            xh = T.x0 + lx;
+            if (nu == 1) {
+                y = side ? T.y0 + T.ty : T.y0 - 1;
+                z = T.z0 + rest % T.tz;
+                t = T.t0 + rest / T.tz;
+            } else if (nu == 2) {
+                y = T.y0 + rest % T.ty;
+                z = side ? T.z0 + T.tz : T.z0 - 1;
+                t = T.t0 + rest / T.ty;
+            } else {
+                y = T.y0 + rest % T.ty;
+                z = T.z0 + rest / T.ty;
+                t = side ? T.t0 + T.tt : T.t0 - 1;
+            }
+        }
+        xh = wrap(xh, a.g.nxh);
+        y = wrap(y, a.g.ny);
+        z = wrap(z, a.g.nz);
+        t = wrap(t, a.g.nt);
+        const int64_t gs = xh + (int64_t)a.g.nxh * (y + (int64_t)a.g.ny * (z + (int64_t)a.g.nz * t));
+#pragma unroll
+        for (int k = 0; k < ST::NP; ++k)
+            *reinterpret_cast<V*>(lds + ((int64_t)k * T.nslots + j) * ST::VB) =
+                ld_plane<V>(src, pb, k, (uint32_t)gs * ST::VB);
+    }
+}
+
+// Where this thread's site finds its staged neighbours in an LDS-staged
+// pass: the slots of U_mu(x + nu) and U_mu(x - nu) for every nu.
+struct lq_site {
+    const char* lds = nullptr;
+    int nslots = 0;
+    int fwd[4] = {0, 0, 0, 0}, bwd[4] = {0, 0, 0, 0};
+};
+
+template <class ST, int KIND, bool REUNIT, int RNG, int MU = -1, bool LQ = false>
+LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site()) {
     using T = typename ST::real;
     using M = m3<T>;
     __shared__ uint32_t rl_lds[RNG == LAT_RNG_RANLUX_I ? 24 * 256 : 1];  // current RANLUX block
@@ -146,9 +308,12 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s) {
         const int64_t s_mn = half_index(a.g, step(a.g, c, nu, -1));
         const int64_t s_pmmn = half_index(a.g, step(a.g, cpm, nu, -1));
         const M f0 = load_link<ST>(L, vp, q, nu, s_pm);
-        const M f1 = load_link<ST>(L, vp, q, mu, s_pn);
+        M f1, b0;
+        if constexpr (LQ) f1 = ST::load(lq.lds, lq.nslots, lq.fwd[nu]);
+        else f1 = load_link<ST>(L, vp, q, mu, s_pn);
         const M f2 = load_link<ST>(L, vp, p, nu, s);
-        const M b0 = load_link<ST>(L, vp, q, mu, s_mn);
+        if constexpr (LQ) b0 = ST::load(lq.lds, lq.nslots, lq.bwd[nu]);
+        else b0 = load_link<ST>(L, vp, q, mu, s_mn);
         const M b1 = load_link<ST>(L, vp, p, nu, s_pmmn);
         const M b2 = load_link<ST>(L, vp, q, nu, s_mn);
         if constexpr (PREPARE) {
@@ -225,6 +390,61 @@ template <class ST, int KIND, bool REUNIT, int RNG, int MU>
 __global__ void __launch_bounds__(256) su3_pass(PassArgs a) {
     const int64_t s = thread_site(a);
     if (s >= 0) su3_site<ST, KIND, REUNIT, RNG, MU>(a, s);
+    if constexpr (KIND == 1) pass_bump(a);
+}
+
+// The same pass with the tile's opposite-parity U_mu links staged in LDS
+// (4-D tiles that divide the lattice; the host checks both).
+template <class ST, int KIND, bool REUNIT, int RNG, int MU>
+__global__ void __launch_bounds__(256) su3_pass_lq(PassArgs a) {
+    extern __shared__ __align__(16) char lq_lds[];
+    int bx, by, bz, bt;
+    if (a.tile_order == 4) {
+        const int64_t nb = gridDim.x, b = blockIdx.x;
+        const int64_t k = b & 7, per = nb >> 3, rem = nb & 7;
+        int64_t j = b >> 3;
+        const int64_t mine = per + (k < rem ? 1 : 0);
+        if (a.reverse) j = mine - 1 - j;
+        int64_t r = k * per + (k < rem ? k : rem) + j;
+        bx = (int)(r % a.tcount[0]);
+        r /= a.tcount[0];
+        by = (int)(r % a.tcount[1]);
+        r /= a.tcount[1];
+        bt = (int)(r % a.tcount[3]);
+        bz = (int)(r / a.tcount[3]);
+    } else {
+        int64_t r = blockIdx.x;
+        bx = (int)(r % a.tcount[0]);
+        r /= a.tcount[0];
+        by = (int)(r % a.tcount[1]);
+        r /= a.tcount[1];
+        bz = (int)(r % a.tcount[2]);
+        bt = (int)(r / a.tcount[2]);
+    }
+    const int mu = MU >= 0 ? MU : a.mu;
+    const lq_tile T = lq_make(mu, bx, by, bz, bt, a.tshape);
+    lq_fill<ST>(a, T, mu, 1 - a.parity, lq_lds);
+    __syncthreads();
+    int i = threadIdx.x;
+    const int lx = i % T.tx;
+    i /= T.tx;
+    const int ly = i % T.ty;
+    i /= T.ty;
+    const int lz = i % T.tz;
+    const int lt = i / T.tz;
+    const int y = T.y0 + ly, z = T.z0 + lz, t = T.t0 + lt;
+    const int r = (a.parity + y + z + t) & 1;  // x = 2 (x0 + lx) + r
+    lq_site ls;
+    ls.lds = lq_lds;
+    ls.nslots = T.nslots;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        ls.fwd[nu] = lq_slot(T, nu, +1, lx, ly, lz, lt, r);
+        ls.bwd[nu] = lq_slot(T, nu, -1, lx, ly, lz, lt, r);
+    }
+    const int64_t s = (T.x0 + lx) + (int64_t)a.g.nxh * (y + (int64_t)a.g.ny * (z + (int64_t)a.g.nz * t));
+    su3_site<ST, KIND, REUNIT, RNG, MU, true>(a, s, ls);
     if constexpr (KIND == 1) pass_bump(a);
 }
 
@@ -928,6 +1148,27 @@ LAT_HOST_DEV_INLINE unsigned pass_blocks(const PassArgs& a, int block) {
 template <class ST, int KIND, bool RE, int RNG>
 hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
     const unsigned nb = pass_blocks(a, block);
+    if constexpr (RNG != LAT_RNG_RANLUX_I) {
+        if (a.stage_lds) {
+            const size_t lds = (size_t)a.stage_lds;
+            // overrelaxation of the compressed and FP32 forms runs best
+            // specialised per direction; the FP64 18-real form (whose
+            // specialised form needs more registers than a wave has) and the
+            // heat bath take the direction at run time
+            constexpr bool PER_MU = KIND == 1 && !std::is_same<ST, st_f64>::value;
+            if constexpr (PER_MU) {
+                switch (a.mu) {
+                    case 0: hipLaunchKernelGGL((su3_pass_lq<ST, KIND, RE, RNG, 0>), dim3(nb), dim3(block), lds, st, a); break;
+                    case 1: hipLaunchKernelGGL((su3_pass_lq<ST, KIND, RE, RNG, 1>), dim3(nb), dim3(block), lds, st, a); break;
+                    case 2: hipLaunchKernelGGL((su3_pass_lq<ST, KIND, RE, RNG, 2>), dim3(nb), dim3(block), lds, st, a); break;
+                    default: hipLaunchKernelGGL((su3_pass_lq<ST, KIND, RE, RNG, 3>), dim3(nb), dim3(block), lds, st, a); break;
+                }
+            } else {
+                hipLaunchKernelGGL((su3_pass_lq<ST, KIND, RE, RNG, -1>), dim3(nb), dim3(block), lds, st, a);
+            }
+            return hipGetLastError();
+        }
+    }
     if constexpr (KIND == 1) {
         switch (a.mu) {
             case 0: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 0>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;

@@ -43,6 +43,7 @@ struct PassArgs {
     int frozen;            // 1: spatial links at t = 0 are not updated
     uint64_t* bump_counter = nullptr;  // heat-bath counter the pass advances ...
     int bump_by = 0;                   // ... by this much when it is done (0: none)
+    int stage_lds = 0;                 // dynamic LDS bytes of the tile's staged U_mu links (0: none)
 };
 
 // Initialisation of one lattice.

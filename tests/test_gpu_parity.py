@@ -384,7 +384,9 @@ def test_autotune_keeps_the_chain(tmp_path, monkeypatch):
         before = a.get_links()
         info0 = a.info()
         shape = a.autotune(1, 4)
-        assert shape["block_size"] in (64, 128, 256) and shape["tile_order"] in (0, 1)
+        assert shape["block_size"] in (64, 128, 256) and shape["tile_order"] in (0, 1, 4)
+        kinds = a.launch_shapes()
+        assert kinds["overrelaxation"]["block_size"] == shape["block_size"]
         assert np.array_equal(a.get_links(), before) and a.info() == info0
         a.sweep(1, 4)
         b.sweep(1, 4)
@@ -394,7 +396,7 @@ def test_autotune_keeps_the_chain(tmp_path, monkeypatch):
         assert c.autotune(1, 4) == shape
     import json
     cache = json.loads((tmp_path / "tune.txt").read_text())
-    assert len(cache) == 2 and all(len(v) == 3 for v in cache.values())
+    assert len(cache) == 2 and all(len(v) == 16 for v in cache.values())
 
 
 def test_full_size_64x16_heat_bath_sweep(tmp_path, monkeypatch):
