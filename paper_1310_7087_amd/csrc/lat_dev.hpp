@@ -131,6 +131,32 @@ LAT_DEV m3<T> mul_an(const m3<T>& a, const m3<T>& b) {
         }
     return r;
 }
+// Rows 0 and 1 of A * B^dagger and of A * B (row 2 is left as it is: for a
+// product of SU(3) matrices it is conj(row 0 x row 1), see third_row).
+template <class T>
+LAT_DEV void mul_na_rows01(m3<T>& r, const m3<T>& a, const m3<T>& b) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmulj0(a.e[i][0], b.e[j][0]);
+            cmacj(s, a.e[i][1], b.e[j][1]);
+            cmacj(s, a.e[i][2], b.e[j][2]);
+            r.e[i][j] = s;
+        }
+}
+template <class T>
+LAT_DEV void mul_nn_rows01(m3<T>& r, const m3<T>& a, const m3<T>& b) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmul0(a.e[i][0], b.e[0][j]);
+            cmac(s, a.e[i][1], b.e[1][j]);
+            cmac(s, a.e[i][2], b.e[2][j]);
+            r.e[i][j] = s;
+        }
+}
 // C += A * B^dagger
 template <class T>
 LAT_DEV void mac_na(m3<T>& c, const m3<T>& a, const m3<T>& b) {
@@ -526,6 +552,91 @@ LAT_DEV coord4 step(const LatGeom& g, coord4 c, int mu, int d) {
     return c;
 }
 
+// 32-bit site arithmetic for the sweep kernels.  A half lattice has fewer
+// than 2^31 sites on any device (the host refuses larger lattices), so half
+// indices and coordinates fit 32 bits; neighbour indices follow from the
+// site's own index by a stride and a wrap-around correction instead of a
+// full re-encoding.
+struct site32 {
+    int x, y, z, t;  // coordinates
+    uint32_t s;      // half-lattice index
+};
+LAT_DEV site32 site_of(const LatGeom& g, uint32_t s, int p) {
+    const uint32_t nxh = (uint32_t)g.nxh, ny = (uint32_t)g.ny, nz = (uint32_t)g.nz;
+    const uint32_t r = s / nxh;
+    const uint32_t xh = s - r * nxh;
+    const uint32_t r2 = r / ny;
+    const uint32_t y = r - r2 * ny;
+    const uint32_t t = r2 / nz;
+    const uint32_t z = r2 - t * nz;
+    site32 c;
+    c.y = (int)y;
+    c.z = (int)z;
+    c.t = (int)t;
+    c.x = 2 * (int)xh + (int)((p + y + z + t) & 1);
+    c.s = s;
+    return c;
+}
+// The neighbour c + d mu-hat (d = +-1), coordinates and half index.
+LAT_DEV site32 site_step(const LatGeom& g, site32 c, int mu, int d) {
+    switch (mu) {
+        case 0: {
+            int x = c.x + d;
+            x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+            c.s = c.s - (uint32_t)(c.x >> 1) + (uint32_t)(x >> 1);
+            c.x = x;
+            break;
+        }
+        case 1: {
+            const uint32_t st = (uint32_t)g.nxh;
+            int y = c.y + d;
+            if (y < 0) {
+                y += g.ny;
+                c.s += (uint32_t)(g.ny - 1) * st;
+            } else if (y >= g.ny) {
+                y -= g.ny;
+                c.s -= (uint32_t)(g.ny - 1) * st;
+            } else {
+                c.s = d > 0 ? c.s + st : c.s - st;
+            }
+            c.y = y;
+            break;
+        }
+        case 2: {
+            const uint32_t st = (uint32_t)g.nxh * (uint32_t)g.ny;
+            int z = c.z + d;
+            if (z < 0) {
+                z += g.nz;
+                c.s += (uint32_t)(g.nz - 1) * st;
+            } else if (z >= g.nz) {
+                z -= g.nz;
+                c.s -= (uint32_t)(g.nz - 1) * st;
+            } else {
+                c.s = d > 0 ? c.s + st : c.s - st;
+            }
+            c.z = z;
+            break;
+        }
+        default: {
+            const uint32_t st = (uint32_t)g.nxh * (uint32_t)g.ny * (uint32_t)g.nz;
+            int t = c.t + d;
+            if (t < 0) {
+                t += g.nt;
+                c.s += (uint32_t)(g.nt - 1) * st;
+            } else if (t >= g.nt) {
+                t -= g.nt;
+                c.s -= (uint32_t)(g.nt - 1) * st;
+            } else {
+                c.s = d > 0 ? c.s + st : c.s - st;
+            }
+            c.t = t;
+            break;
+        }
+    }
+    return c;
+}
+LAT_DEV coord4 coords(const site32& c) { return {c.x, c.y, c.z, c.t}; }
+
 // Background phase theta of link (c, mu): B = exp(i theta T).
 LAT_DEV double bg_theta(const LatGeom& g, int flux, coord4 c, int mu) {
     if (flux == 0 || mu > 1) return 0.0;
@@ -557,6 +668,7 @@ struct st_f64 {  // SU(3), 18 doubles: 9 planes of (re, im)
     using mat = m3<double>;
     static constexpr int NP = 9;
     static constexpr int VB = 16;
+    static constexpr bool TWO_ROWS = false;  // all three rows are stored
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
         const uint32_t off = (uint32_t)s * VB;
         const int64_t pb = plane_stride * VB;
@@ -581,6 +693,7 @@ struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
     using mat = m3<float>;
     static constexpr int NP = 9;
     static constexpr int VB = 8;
+    static constexpr bool TWO_ROWS = false;
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
         const uint32_t off = (uint32_t)s * VB;
         const int64_t pb = plane_stride * VB;
@@ -605,7 +718,9 @@ struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
     using mat = m3<float>;
     static constexpr int NP = 3;
     static constexpr int VB = 16;
-    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+    static constexpr bool TWO_ROWS = true;  // only rows 0 and 1 are stored
+    // rows 0 and 1 only (row 2 zero)
+    LAT_DEV static mat load_rows01(const char* base, int64_t plane_stride, int64_t s) {
         const uint32_t off = (uint32_t)s * VB;
         const int64_t pb = plane_stride * VB;
         const float4 a = ld_plane<float4>(base, pb, 0, off);
@@ -618,6 +733,11 @@ struct st_f32c12 {  // SU(3), rows 1-2 as 3 planes of float4; row 3 rebuilt
         m.e[1][0] = {b.z, b.w};
         m.e[1][1] = {c.x, c.y};
         m.e[1][2] = {c.z, c.w};
+        m.e[2][0] = m.e[2][1] = m.e[2][2] = {0.f, 0.f};
+        return m;
+    }
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        mat m = load_rows01(base, plane_stride, s);
         third_row(m);
         return m;
     }
@@ -635,7 +755,9 @@ struct st_f64c12 {  // SU(3), rows 1-2 as 6 planes of (re, im) doubles; row 3 re
     using mat = m3<double>;
     static constexpr int NP = 6;
     static constexpr int VB = 16;
-    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+    static constexpr bool TWO_ROWS = true;  // only rows 0 and 1 are stored
+    // rows 0 and 1 only (row 2 zero)
+    LAT_DEV static mat load_rows01(const char* base, int64_t plane_stride, int64_t s) {
         const uint32_t off = (uint32_t)s * VB;
         const int64_t pb = plane_stride * VB;
         mat m;
@@ -644,6 +766,11 @@ struct st_f64c12 {  // SU(3), rows 1-2 as 6 planes of (re, im) doubles; row 3 re
             const double2 v = ld_plane<double2>(base, pb, k, off);
             m.e[k / 3][k % 3] = {v.x, v.y};
         }
+        m.e[2][0] = m.e[2][1] = m.e[2][2] = {0.0, 0.0};
+        return m;
+    }
+    LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
+        mat m = load_rows01(base, plane_stride, s);
         third_row(m);
         return m;
     }
@@ -696,6 +823,10 @@ LAT_DEV const char* dir_base(const char* links, int64_t vh_pad, int p, int mu) {
 template <class ST>
 LAT_DEV typename ST::mat load_link(const char* links, int64_t vh_pad, int p, int mu, int64_t s) {
     return ST::load(dir_base<ST>(links, vh_pad, p, mu), vh_pad, s);
+}
+template <class ST>
+LAT_DEV typename ST::mat load_link_rows01(const char* links, int64_t vh_pad, int p, int mu, int64_t s) {
+    return ST::load_rows01(dir_base<ST>(links, vh_pad, p, mu), vh_pad, s);
 }
 
 }  // namespace latdev
