@@ -66,7 +66,9 @@ extern "C" {
 /* ---- random number generators (one parameter picks it, Sec. 3.4) ---- */
 #define LAT_RNG_MRG32K3A 0  /* per-site MRG32k3a streams, 2^127 apart */
 #define LAT_RNG_PHILOX 1    /* per-site counter-based Philox4x32-10 */
-#define LAT_RNG_CONST 2     /* every uniform = rng_const (debugging, Sec. 3.4) */
+#define LAT_RNG_CONST 2     /* every uniform = rng_const (debugging, Sec. 3.4); an
+                               SU(3) hot start with it is refused (LAT_EINVAL): equal
+                               uniforms give two equal Gaussian rows */
 #define LAT_RNG_RANLUX 3    /* per-site RANLUX, luxury level 3 (the generator of the
                                paper's benchmark runs, Sec. 5): of every 223 outputs
                                of the subtract-with-borrow generator x_n = x_{n-10}

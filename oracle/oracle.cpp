@@ -605,6 +605,9 @@ orc_lattice* orc_create(int group, int nx, int ny, int nz, int nt, double beta, 
     if (rng < 0 || rng > 3) return nullptr;
     if (rng == ORC_RNG_MRG32K3A && (seed < 1 || seed >= MRG_M2)) return nullptr;
     if (frozen != 0 && frozen != 1) return nullptr;
+    // constant uniforms would make the two complex-Gaussian rows of an SU(3)
+    // Haar start equal (Gram-Schmidt then has nothing to orthonormalise)
+    if (group == 3 && rng == ORC_RNG_CONST && start == ORC_HOT) return nullptr;
     orc_lattice* L = new orc_lattice();
     L->frozen = frozen;
     L->n = group;

@@ -29,7 +29,8 @@ typedef struct orc_lattice orc_lattice;
 enum { ORC_RNG_MRG32K3A = 0, ORC_RNG_PHILOX = 1, ORC_RNG_CONST = 2, ORC_RNG_RANLUX = 3 };
 enum { ORC_COLD = 0, ORC_HOT = 1 };
 
-/* Returns NULL on invalid arguments (odd or < 2 extents, group not 2/3).
+/* Returns NULL on invalid arguments (odd or < 2 extents, group not 2/3, an
+ * SU(3) hot start with the constant generator).
  * frozen = 1 holds the spatial links of the time slice t = 0 at the
  * background field (U = 1, W = B) and never updates them: the external field
  * of the paper's Sec. 1 can then no longer be removed by a change of

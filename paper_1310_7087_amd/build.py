@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "liblat.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["lat_kernels.hip", "lat_on.hip", "lat_noalloc.hip", "lat_api.cpp"]
+SOURCES = ["lat_kernels.hip", "lat_on.hip", "lat_noalloc.hip", "lat_api.cpp", "lat_hostio.cpp"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no implicit contraction: fused multiply-adds are written out where

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/lat.h"
+#include "lat_hostio.hpp"
 #include "lat_launch.hpp"
 #include "lat_types.hpp"
 
@@ -611,6 +612,10 @@ int lat_create(lat_t* out, int group, int Nx, int Ny, int Nz, int Nt, double bet
     if (!(beta >= 0.0) || beta > 1e6) return fail(LAT_EINVAL, "beta must be finite and >= 0");
     int rc = check_opts(&o);
     if (rc) return rc;
+    // constant uniforms make the two Gaussian rows of an SU(3) hot start
+    // equal, which Gram-Schmidt cannot orthonormalise
+    if (group == 3 && o.rng == LAT_RNG_CONST && o.start == LAT_HOT)
+        return fail(LAT_EINVAL, "an SU(3) hot start needs a random generator (constant uniforms give equal rows)");
     lat_ctx* h = new lat_ctx();
     h->group = group;
     h->storage = o.storage;
@@ -881,45 +886,17 @@ std::string tune_key(const char* what, const std::vector<int>& v, int storage) {
     return k + "_" + name;
 }
 
-// The tuning cache is a JSON object mapping each key to its chosen shape,
-// {"pass_s0_3_32_32_32_8_gfx950": [128, 0, 1], ...}, in the file named by
-// LAT_TUNE_CACHE (no cache if unset).  Only that flat form is read back;
-// anything else in the file is skipped.
+// The tuning cache (LAT_TUNE_CACHE, no cache if unset): a JSON object
+// mapping each key to its chosen shapes, parsed and written by lathost.
 std::map<std::string, std::vector<int>> tune_cache_read(const char* path) {
-    std::map<std::string, std::vector<int>> m;
     FILE* f = std::fopen(path, "r");
-    if (!f) return m;
+    if (!f) return {};
     std::string t;
     char buf[4096];
     size_t n;
     while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, n);
     std::fclose(f);
-    size_t i = 0;
-    while (true) {
-        const size_t k0 = t.find('"', i);
-        if (k0 == std::string::npos) break;
-        const size_t k1 = t.find('"', k0 + 1);
-        if (k1 == std::string::npos) break;
-        const std::string key = t.substr(k0 + 1, k1 - k0 - 1);
-        const size_t lb = t.find('[', k1), rb = t.find(']', k1);
-        if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
-        std::vector<int> v;
-        const char* c = t.c_str() + lb + 1;
-        const char* end = t.c_str() + rb;
-        while (c < end) {
-            char* e = nullptr;
-            const long x = std::strtol(c, &e, 10);
-            if (e == c) {
-                ++c;
-                continue;
-            }
-            v.push_back((int)x);
-            c = e;
-        }
-        m[key] = v;
-        i = rb + 1;
-    }
-    return m;
+    return lathost::parse_tune_cache(t);
 }
 
 bool tune_cache_get(const std::string& key, std::vector<int>& val) {
@@ -941,17 +918,10 @@ void tune_cache_put(const std::string& key, const std::vector<int>& val) {
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "{");
-    bool first = true;
-    for (const auto& kv : m) {
-        std::fprintf(f, "%s\n  \"%s\": [", first ? "" : ",", kv.first.c_str());
-        for (size_t j = 0; j < kv.second.size(); ++j) std::fprintf(f, "%s%d", j ? ", " : "", kv.second[j]);
-        std::fprintf(f, "]");
-        first = false;
-    }
-    std::fprintf(f, "\n}\n");
-    const bool ok = std::fclose(f) == 0;
-    if (ok) std::rename(tmp.c_str(), path);
+    const std::string text = lathost::format_tune_cache(m);
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    if ((std::fclose(f) == 0) && ok) std::rename(tmp.c_str(), path);
+    else std::remove(tmp.c_str());
 }
 
 // Owners that release a device buffer or an event on every way out of a
@@ -1199,26 +1169,6 @@ int lat_philox4x32_10(const uint32_t* ctr, const uint32_t key[2], uint32_t* out,
 // ===========================================================================
 namespace {
 
-const char CKPT_MAGIC[8] = {'L', 'A', 'T', 'C', 'K', 'P', 'T', '1'};
-
-struct CkptHeader {
-    char magic[8];
-    uint32_t version, group, dims[4], storage, rng, start, nhit;
-    int32_t flux;
-    uint32_t lat_id, frozen, reserved;
-    double beta, rng_const;
-    uint64_t seed, hb_sweeps, sweeps, n_doubles, n_mrg;
-};
-
-uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
-    const unsigned char* c = (const unsigned char*)p;
-    for (size_t i = 0; i < n; ++i) {
-        h ^= c[i];
-        h *= 1099511628211ull;
-    }
-    return h;
-}
-
 }  // namespace
 
 extern "C" int lat_save(lat_t h, const char* path) {
@@ -1232,10 +1182,8 @@ extern "C" int lat_save(lat_t h, const char* path) {
         rc = lat_get_rng_state(h, mrg.data(), mrg.size());
         if (rc) return rc;
     }
-    CkptHeader hd;
-    std::memset(&hd, 0, sizeof hd);
-    std::memcpy(hd.magic, CKPT_MAGIC, 8);
-    hd.version = 2;
+    lathost::su_header hd;
+    lathost::su_header_init(hd);
     hd.group = (uint32_t)h->group;
     for (int m = 0; m < 4; ++m) hd.dims[m] = (uint32_t)h->dims[m];
     hd.storage = (uint32_t)h->storage;
@@ -1252,55 +1200,25 @@ extern "C" int lat_save(lat_t h, const char* path) {
     hd.sweeps = h->sweeps;
     hd.n_doubles = links.size();
     hd.n_mrg = mrg.size();
-    uint64_t sum = 1469598103934665603ull;
-    sum = fnv1a(sum, &hd, sizeof hd);
-    sum = fnv1a(sum, links.data(), links.size() * sizeof(double));
-    if (!mrg.empty()) sum = fnv1a(sum, mrg.data(), mrg.size() * 4);
-    std::string tmp = std::string(path) + ".tmp";
-    FILE* f = std::fopen(tmp.c_str(), "wb");
-    if (!f) return fail(LAT_EIO, "cannot open %s", tmp.c_str());
-    bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1;
-    ok = ok && std::fwrite(links.data(), sizeof(double), links.size(), f) == links.size();
-    if (!mrg.empty()) ok = ok && std::fwrite(mrg.data(), 4, mrg.size(), f) == mrg.size();
-    ok = ok && std::fwrite(&sum, sizeof sum, 1, f) == 1;
-    ok = (std::fclose(f) == 0) && ok;
-    if (!ok || std::rename(tmp.c_str(), path) != 0) {
-        std::remove(tmp.c_str());
+    if (!lathost::write_checkpoint(path, &hd, sizeof hd, links.data(), links.size(), mrg.data(), mrg.size()))
         return fail(LAT_EIO, "write of %s failed", path);
-    }
     return LAT_OK;
 }
 
 extern "C" int lat_load(lat_t* out, const char* path, const lat_options* opt) {
     if (!out || !path) return fail(LAT_EINVAL, "NULL argument");
     *out = nullptr;
-    FILE* f = std::fopen(path, "rb");
-    if (!f) return fail(LAT_EIO, "cannot open %s", path);
-    CkptHeader hd;
-    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, CKPT_MAGIC, 8) != 0 || hd.version != 2) {
-        std::fclose(f);
-        return fail(LAT_ECORRUPT, "%s is not a lattice checkpoint", path);
+    lathost::su_header hd;
+    std::vector<double> links;
+    std::vector<uint32_t> mrg;
+    switch (lathost::read_su_checkpoint(path, hd, links, mrg)) {
+        case lathost::CKPT_OK: break;
+        case lathost::CKPT_CANNOT_OPEN: return fail(LAT_EIO, "cannot open %s", path);
+        case lathost::CKPT_BAD_HEADER: return fail(LAT_ECORRUPT, "%s is not a lattice checkpoint (or its header is inconsistent)", path);
+        case lathost::CKPT_BAD_SIZE: return fail(LAT_ECORRUPT, "%s is truncated or has trailing data", path);
+        case lathost::CKPT_NO_MEMORY: return fail(LAT_ENOMEM, "no host memory for %s", path);
+        default: return fail(LAT_ECORRUPT, "checksum mismatch in %s", path);
     }
-    const uint64_t V = (uint64_t)hd.dims[0] * hd.dims[1] * hd.dims[2] * hd.dims[3];
-    if ((hd.group != 2 && hd.group != 3) || hd.n_doubles != V * 4 * (uint64_t)ncomp((int)hd.group) ||
-        hd.rng > (uint32_t)LAT_RNG_RANLUX || hd.n_mrg != V * (uint64_t)rng_words((int)hd.rng)) {
-        std::fclose(f);
-        return fail(LAT_ECORRUPT, "inconsistent checkpoint header in %s", path);
-    }
-    std::vector<double> links(hd.n_doubles);
-    std::vector<uint32_t> mrg(hd.n_mrg);
-    uint64_t stored = 0;
-    bool ok = std::fread(links.data(), sizeof(double), links.size(), f) == links.size();
-    if (!mrg.empty()) ok = ok && std::fread(mrg.data(), 4, mrg.size(), f) == mrg.size();
-    ok = ok && std::fread(&stored, sizeof stored, 1, f) == 1;
-    std::fclose(f);
-    if (!ok) return fail(LAT_ECORRUPT, "%s is truncated", path);
-    uint64_t sum = 1469598103934665603ull;
-    sum = fnv1a(sum, &hd, sizeof hd);
-    sum = fnv1a(sum, links.data(), links.size() * sizeof(double));
-    if (!mrg.empty()) sum = fnv1a(sum, mrg.data(), mrg.size() * 4);
-    if (sum != stored) return fail(LAT_ECORRUPT, "checksum mismatch in %s", path);
-
     lat_options o;
     lat_default_options(&o);
     if (opt) o = *opt;

@@ -25,6 +25,7 @@
 
 #include "../../include/lat.h"
 #include "lat_dev.hpp"
+#include "lat_hostio.hpp"
 #include "lat_launch.hpp"
 
 using namespace latdev;
@@ -585,24 +586,6 @@ int create_device(lat_on_ctx* c, const lat_options& o) {
     return LAT_OK;
 }
 
-const char ON_MAGIC[8] = {'L', 'A', 'T', 'O', 'N', 'C', 'K', '1'};
-
-struct OnCkptHeader {
-    char magic[8];
-    uint32_t version, ncomp, dims[4], storage, rng, start, nhit, lat_id, reserved;
-    double kappa, lambda, h, delta, rng_const;
-    uint64_t seed, sweeps, n_doubles, n_words;
-};
-
-uint64_t on_fnv1a(uint64_t h, const void* p, size_t n) {
-    const unsigned char* b = (const unsigned char*)p;
-    for (size_t i = 0; i < n; ++i) {
-        h ^= b[i];
-        h *= 1099511628211ull;
-    }
-    return h;
-}
-
 }  // namespace
 
 extern "C" {
@@ -807,10 +790,8 @@ int lat_on_save(lat_on_t c, const char* path) {
         words.resize((size_t)c->V() * state_words(c->rng));
         if ((rc = rl_transfer(c, words.data(), false))) return rc;
     }
-    OnCkptHeader hd;
-    std::memset(&hd, 0, sizeof hd);
-    std::memcpy(hd.magic, ON_MAGIC, 8);
-    hd.version = 1;
+    lathost::on_header hd;
+    lathost::on_header_init(hd);
     hd.ncomp = (uint32_t)c->n;
     hd.dims[0] = (uint32_t)c->g.nx;
     hd.dims[1] = (uint32_t)c->g.ny;
@@ -830,55 +811,25 @@ int lat_on_save(lat_on_t c, const char* path) {
     hd.sweeps = c->sweeps;
     hd.n_doubles = field.size();
     hd.n_words = words.size();
-    uint64_t sum = 1469598103934665603ull;
-    sum = on_fnv1a(sum, &hd, sizeof hd);
-    sum = on_fnv1a(sum, field.data(), field.size() * sizeof(double));
-    if (!words.empty()) sum = on_fnv1a(sum, words.data(), words.size() * 4);
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* f = std::fopen(tmp.c_str(), "wb");
-    if (!f) return lat_internal_fail(LAT_EIO, ("cannot open " + tmp).c_str());
-    bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1;
-    ok = ok && std::fwrite(field.data(), sizeof(double), field.size(), f) == field.size();
-    if (!words.empty()) ok = ok && std::fwrite(words.data(), 4, words.size(), f) == words.size();
-    ok = ok && std::fwrite(&sum, sizeof sum, 1, f) == 1;
-    ok = (std::fclose(f) == 0) && ok;
-    if (!ok || std::rename(tmp.c_str(), path) != 0) {
-        std::remove(tmp.c_str());
+    if (!lathost::write_checkpoint(path, &hd, sizeof hd, field.data(), field.size(), words.data(), words.size()))
         return lat_internal_fail(LAT_EIO, (std::string("write of ") + path + " failed").c_str());
-    }
     return LAT_OK;
 }
 
 int lat_on_load(lat_on_t* out, const char* path, const lat_options* opt) {
     if (!out || !path) return lat_internal_fail(LAT_EINVAL, "NULL argument");
     *out = nullptr;
-    FILE* f = std::fopen(path, "rb");
-    if (!f) return lat_internal_fail(LAT_EIO, (std::string("cannot open ") + path).c_str());
-    OnCkptHeader hd;
-    if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, ON_MAGIC, 8) != 0 || hd.version != 1 ||
-        hd.ncomp < 1 || hd.ncomp > 4) {
-        std::fclose(f);
-        return lat_internal_fail(LAT_ECORRUPT, "not an O(N) checkpoint");
+    lathost::on_header hd;
+    std::vector<double> field;
+    std::vector<uint32_t> words;
+    switch (lathost::read_on_checkpoint(path, hd, field, words)) {
+        case lathost::CKPT_OK: break;
+        case lathost::CKPT_CANNOT_OPEN: return lat_internal_fail(LAT_EIO, (std::string("cannot open ") + path).c_str());
+        case lathost::CKPT_BAD_HEADER: return lat_internal_fail(LAT_ECORRUPT, "not an O(N) checkpoint (or its header is inconsistent)");
+        case lathost::CKPT_BAD_SIZE: return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint is truncated or has trailing data");
+        case lathost::CKPT_NO_MEMORY: return lat_internal_fail(LAT_ENOMEM, "no host memory for the O(N) checkpoint");
+        default: return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint checksum mismatch");
     }
-    const uint64_t V = (uint64_t)hd.dims[0] * hd.dims[1] * hd.dims[2] * hd.dims[3];
-    if (V == 0 || V > ((uint64_t)1 << 32) || hd.n_doubles != V * hd.ncomp ||
-        hd.rng > LAT_RNG_RANLUX || hd.n_words != V * (uint64_t)state_words((int)hd.rng)) {
-        std::fclose(f);
-        return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint sizes do not match its header");
-    }
-    std::vector<double> field(hd.n_doubles);
-    std::vector<uint32_t> words(hd.n_words);
-    uint64_t sum = 0;
-    bool ok = std::fread(field.data(), sizeof(double), field.size(), f) == field.size();
-    if (!words.empty()) ok = ok && std::fread(words.data(), 4, words.size(), f) == words.size();
-    ok = ok && std::fread(&sum, sizeof sum, 1, f) == 1;
-    std::fclose(f);
-    if (!ok) return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint is truncated");
-    uint64_t want = 1469598103934665603ull;
-    want = on_fnv1a(want, &hd, sizeof hd);
-    want = on_fnv1a(want, field.data(), field.size() * sizeof(double));
-    if (!words.empty()) want = on_fnv1a(want, words.data(), words.size() * 4);
-    if (want != sum) return lat_internal_fail(LAT_ECORRUPT, "O(N) checkpoint checksum mismatch");
     lat_options o;
     lat_default_options(&o);
     if (opt) o = *opt;

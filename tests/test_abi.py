@@ -63,6 +63,7 @@ def test_device_bytes_layout():
     (3, (4, 4, 4, 4), 5.7, {"nhit": 128}, -1),
     (3, (4, 4, 4, 4), 5.7, {"rng": 7}, -1),
     (3, (4, 4, 4, 4), 5.7, {"rng": 2, "rng_const": 1.0}, -1),
+    (3, (4, 4, 4, 4), 5.7, {"rng": 2, "start": 1}, -1),
     (3, (4, 4, 4, 4), 5.7, {"block_size": 100}, -1),
     (2, (4, 4, 4, 4), 2.3, {"storage": 2}, -7),
     (2, (4, 4, 4, 4), 2.3, {"storage": 3}, -7),
@@ -143,3 +144,23 @@ def test_o_n_layout_and_rejections_without_a_device():
         with pytest.raises(P.LatError) as e:
             P.ONField(args.pop("ncomp"), args.pop("dims"), args.pop("kappa"), args.pop("lam"), **args)
         assert e.value.code == code, kw
+
+
+def test_loaders_reject_corrupt_files_without_a_device(tmp_path):
+    """Checkpoint readers check header, size and checksum before any device
+    call: garbage, an empty file and a truncated header give LAT_ECORRUPT,
+    a missing file LAT_EIO."""
+    import ctypes
+    import paper_1310_7087_amd as P
+    bad = tmp_path / "bad.ckpt"
+    cases = [(b"", P.ECORRUPT), (b"LATCKPT1" + b"\x02\x00\x00\x00", P.ECORRUPT),
+             (bytes(range(256)) * 4, P.ECORRUPT)]
+    for raw, code in cases:
+        bad.write_bytes(raw)
+        h = ctypes.c_void_p()
+        assert P.lib.lat_load(ctypes.byref(h), str(bad).encode(), None) == code
+        assert P.lib.lat_on_load(ctypes.byref(h), str(bad).encode(), None) == code
+        assert not h.value
+    h = ctypes.c_void_p()
+    assert P.lib.lat_load(ctypes.byref(h), str(tmp_path / "missing").encode(), None) == P.EIO
+    assert P.lib.lat_on_load(ctypes.byref(h), str(tmp_path / "missing").encode(), None) == P.EIO
