@@ -302,7 +302,9 @@ typedef struct {
  * results are bit-identical to the same lattice run alone. */
 int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_options* common);
 /* Launch form and shape.  mode 0 (default): one kernel per pass index, each
- * covering that pass of every member (kernel boundaries order the passes);
+ * covering that pass of every member (kernel boundaries order the passes),
+ * every member whole on one XCD; mode 2: the same with the members' tiles
+ * dealt round the XCDs (see lat_batch_autotune);
  * mode 1, a persistent work-list kernel for all passes with per-member
  * dependency counters, is switched off and returns LAT_EUNSUPPORTED.
  * block_size 64|128|256, sites_per_thread 1..8 per work item, grid = blocks
@@ -310,11 +312,17 @@ int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, const lat_optio
  * and shape gives bit-identical results. */
 int lat_batch_configure(lat_batch_t b, int mode, int block_size, int sites_per_thread, int grid);
 /* Autotuner of the batch launch: times every work-group size (64, 128,
- * 256) and sites per thread (1, 2, 4) on compound sweeps (n_hb, n_or) of
- * the whole batch, keeps the fastest and restores every member's state
- * (cache file as for lat_autotune).  result (optional) = {size, sites per
- * thread}.  Synchronises. */
+ * 256) x sites per thread (1, 2, 4) x XCD map -- 0: every member whole on
+ * one XCD (members packed largest first onto the XCD with the least work,
+ * so a member's neighbour links stay in one L2; the default), 1: the
+ * members' tiles dealt round the XCDs (a member larger than one L2 spreads
+ * over all of them) -- on compound sweeps (n_hb, n_or) of the whole batch,
+ * keeps the fastest and restores every member's state (cache file as for
+ * lat_autotune).  result (optional) = {size, sites per thread}.
+ * Synchronises. */
 int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[2]);
+/* Current batch launch shape: {work-group size, sites per thread, XCD map}. */
+int lat_batch_get_shape(lat_batch_t b, int shape[3]);
 /* n_sweeps compound sweeps of every member; if plaq / poly are non-NULL they
  * receive each member's final measurement ([n][3] and [n][2]); synchronises. */
 int lat_batch_run(lat_batch_t b, int n_sweeps, int n_hb, int n_or, double* plaq, double* poly);

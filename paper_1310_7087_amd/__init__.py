@@ -109,6 +109,7 @@ def _load():
     L.lat_batch_run.argtypes = [vp, i, i, i, vp, vp]
     L.lat_batch_configure.argtypes = [vp, i, i, i, i]
     L.lat_batch_autotune.argtypes = [vp, i, i, vp]
+    L.lat_batch_get_shape.argtypes = [vp, vp]
     L.lat_batch_get_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_set_links.argtypes = [vp, i, vp, sz]
     L.lat_batch_destroy.argtypes = [vp]
@@ -133,7 +134,7 @@ def _load():
                  "lat_get_rng_state", "lat_get_info", "lat_profile_passes", "lat_autotune", "lat_get_launch_shape", "lat_set_accept_log", "lat_save", "lat_load",
                  "lat_destroy", "lat_philox4x32_10", "lat_batch_create", "lat_batch_run",
                  "lat_batch_get_links", "lat_batch_set_links", "lat_batch_destroy", "lat_batch_configure",
-                 "lat_batch_autotune"):
+                 "lat_batch_autotune", "lat_batch_get_shape"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -372,7 +373,12 @@ class Batch:
     def autotune(self, n_hb=1, n_or=4) -> dict:
         r = np.zeros(2, dtype=np.int32)
         _check(lib.lat_batch_autotune(self._h, int(n_hb), int(n_or), _ptr(r)))
-        return {"block_size": int(r[0]), "sites_per_thread": int(r[1])}
+        return {"block_size": int(r[0]), "sites_per_thread": int(r[1]), "xcd_map": self.shape()["xcd_map"]}
+
+    def shape(self) -> dict:
+        r = np.zeros(3, dtype=np.int32)
+        _check(lib.lat_batch_get_shape(self._h, _ptr(r)))
+        return {"block_size": int(r[0]), "sites_per_thread": int(r[1]), "xcd_map": int(r[2])}
 
     def get_links(self, i) -> np.ndarray:
         d = self.descs[i]

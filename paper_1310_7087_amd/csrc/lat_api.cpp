@@ -7,6 +7,7 @@
 // replayed; steady-state sweeps never touch the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
@@ -1286,6 +1287,10 @@ struct lat_batch {
     BatchLat* d_lats = nullptr;       // device table
     uint64_t** d_counters = nullptr;  // members' heat-bath counters
     unsigned* d_work = nullptr;       // [0] queue, [1] status, [2..] done per member
+    BatchItem* d_items = nullptr;     // work-group -> (member, tile) of a pass launch
+    size_t items_cap = 0;
+    int nitems = 0;
+    int map = 0;  // 0: each member whole on one XCD; 1: a member's tiles dealt round the XCDs
     int tiles_per_pass = 0;
     int block = 256, spt = 1, grid = 0;
     int mode = 0;  // 0: one launch per pass, 1: persistent work list
@@ -1294,6 +1299,14 @@ struct lat_batch {
 };
 
 namespace {
+
+void batch_drop_graphs(lat_batch* b) {
+    for (auto& kv : b->graphs) {
+        if (kv.second.exec) discard(hipGraphExecDestroy(kv.second.exec));
+        if (kv.second.graph) discard(hipGraphDestroy(kv.second.graph));
+    }
+    b->graphs.clear();
+}
 
 int batch_build_table(lat_batch* b) {
     const int n = (int)b->members.size();
@@ -1322,6 +1335,49 @@ int batch_build_table(lat_batch* b) {
         ctr[i] = h->hb();
     }
     b->tiles_per_pass = prefix;
+    // Work-group -> (member, tile) map of a pass launch; captured graphs hold
+    // the table, so they are dropped whenever it is rebuilt.  Work-group
+    // j*8 + k runs on XCD k.  map 0: each member goes whole to one XCD
+    // (largest first, to the XCD with the least work so far, work = tiles x
+    // link bytes), so the neighbours a member's sites read stay in one L2;
+    // each XCD takes its members' tiles in order, shorter lists padded with
+    // empty items.  map 1: the members' tiles in order, dealt round the XCDs
+    // (a member larger than one L2 then spreads over all of them).
+    batch_drop_graphs(b);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto weight = [&](int i) { return (double)t[i].ntiles * (double)bytes_per_link(t[i].group, b->storage); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return weight(a) > weight(c); });
+    std::vector<std::vector<BatchItem>> per_xcd(8);
+    std::vector<double> load(8, 0.0);
+    for (int i : order) {
+        int k = 0;
+        for (int x = 1; x < 8; ++x)
+            if (load[x] < load[k]) k = x;
+        load[k] += weight(i);
+        for (int tl = 0; tl < t[i].ntiles; ++tl) per_xcd[k].push_back({i, tl});
+    }
+    size_t longest = 0;
+    for (const auto& v : per_xcd) longest = v.size() > longest ? v.size() : longest;
+    std::vector<BatchItem> items;
+    if (b->map == 0) {
+        items.assign(longest * 8, BatchItem{-1, 0});
+        for (int k = 0; k < 8; ++k)
+            for (size_t j = 0; j < per_xcd[k].size(); ++j) items[j * 8 + k] = per_xcd[k][j];
+    } else {
+        for (int i = 0; i < n; ++i)
+            for (int tl = 0; tl < t[i].ntiles; ++tl) items.push_back({i, tl});
+    }
+    if (items.size() > b->items_cap) {
+        if (b->d_items) HIP_TRY(hipFree(b->d_items));
+        b->d_items = nullptr;
+        b->items_cap = 0;
+        HIP_TRY(hipMalloc(&b->d_items, sizeof(BatchItem) * items.size()));
+        b->items_cap = items.size();
+    }
+    b->nitems = (int)items.size();
+    HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice,
+                           b->stream));
     if (!b->d_lats) HIP_TRY(hipMalloc(&b->d_lats, sizeof(BatchLat) * n));
     if (!b->d_counters) HIP_TRY(hipMalloc(&b->d_counters, sizeof(uint64_t*) * n));
     if (!b->d_work) HIP_TRY(hipMalloc(&b->d_work, sizeof(unsigned) * (n + 2)));
@@ -1333,13 +1389,6 @@ int batch_build_table(lat_batch* b) {
     return LAT_OK;
 }
 
-void batch_drop_graphs(lat_batch* b) {
-    for (auto& kv : b->graphs) {
-        if (kv.second.exec) discard(hipGraphExecDestroy(kv.second.exec));
-        if (kv.second.graph) discard(hipGraphDestroy(kv.second.graph));
-    }
-    b->graphs.clear();
-}
 
 BatchArgs batch_args(const lat_batch* b, int n_sweeps, int n_hb, int n_or) {
     BatchArgs a;
@@ -1355,11 +1404,13 @@ BatchArgs batch_args(const lat_batch* b, int n_sweeps, int n_hb, int n_or) {
     a.status = reinterpret_cast<int*>(b->d_work + 1);
     a.done = b->d_work + 2;
     a.spin_limit = 1u << 22;  // ~2 s of polling: far beyond any legitimate wait
+    a.items = b->d_items;
+    a.nitems = b->nitems;
     return a;
 }
 
 int batch_enqueue(lat_batch* b, int n_sweeps, int n_hb, int n_or) {
-    auto key = std::make_tuple(n_sweeps, n_hb, n_or, b->block, b->spt, b->grid, b->mode);
+    auto key = std::make_tuple(n_sweeps, n_hb, n_or, b->block, b->spt, b->grid, b->mode * 2 + b->map);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         BatchGraph g;
@@ -1462,7 +1513,8 @@ extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, cons
 
 extern "C" int lat_batch_configure(lat_batch_t b, int mode, int block_size, int sites_per_thread, int grid) {
     if (!b) return fail(LAT_EINVAL, "NULL batch");
-    if (mode != 0 && mode != 1) return fail(LAT_EINVAL, "mode 0 (per-pass launches) or 1 (persistent)");
+    if (mode < 0 || mode > 2)
+        return fail(LAT_EINVAL, "mode 0 or 2 (per-pass launches, XCD map 0 or 1) or 1 (persistent)");
     // The persistent work-list form did not finish within its test's time
     // limit on MI355X (dependency polling across XCDs); it stays switched off
     // until the cause is shown.
@@ -1471,7 +1523,8 @@ extern "C" int lat_batch_configure(lat_batch_t b, int mode, int block_size, int 
     if (sites_per_thread < 1 || sites_per_thread > 8) return fail(LAT_EINVAL, "sites_per_thread 1..8");
     if (grid < 0) return fail(LAT_EINVAL, "grid >= 0");
     HIP_TRY(hipStreamSynchronize(b->stream));
-    b->mode = mode;
+    b->mode = mode == 2 ? 0 : mode;
+    b->map = mode == 2 ? 1 : 0;
     b->block = block_size;
     b->spt = sites_per_thread;
     b->grid = grid ? grid : device_cus() * (1024 / block_size);
@@ -1491,7 +1544,7 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
     // a compact key: member count plus a hash of the member shapes
     uint64_t hsh = 1469598103934665603ull;
     for (int x : key_v) hsh = (hsh ^ (uint64_t)(uint32_t)x) * 1099511628211ull;
-    const std::string key = tune_key("batch", {(int)b->members.size(), (int)(hsh & 0x7fffffff)}, b->storage);
+    const std::string key = tune_key("batchmap", {(int)b->members.size(), (int)(hsh & 0x7fffffff)}, b->storage);
     std::vector<int> best;
     if (!tune_cache_get(key, best)) {
         std::vector<char*> backup(b->members.size(), nullptr);
@@ -1507,14 +1560,15 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
         }
         std::vector<std::pair<uint64_t, uint64_t>> counters;
         for (lat_t h : b->members) counters.emplace_back(h->hb_sweeps, h->sweeps);
-        const int keep_block = b->block, keep_spt = b->spt;
+        const int keep_block = b->block, keep_spt = b->spt, keep_map = b->map;
         double best_ms = 1e30;
         const int blocks[3] = {64, 128, 256};
         const int spts[3] = {1, 2, 4};
         for (int bi = 0; bi < 3 && !rc; ++bi)
-            for (int si = 0; si < 3 && !rc; ++si) {
+            for (int si = 0; si < 6 && !rc; ++si) {
                 b->block = blocks[bi];
-                b->spt = spts[si];
+                b->spt = spts[si % 3];
+                b->map = si / 3;
                 rc = batch_build_table(b);
                 if (rc) break;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1546,7 +1600,7 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
                         rc = fail(LAT_EDEVICE, "autotune timing");
                     if (!rc && t / 2 < best_ms) {
                         best_ms = t / 2;
-                        best = {blocks[bi], spts[si], 0};
+                        best = {blocks[bi], spts[si % 3], si / 3};
                     }
                 }
                 discard(hipEventDestroy(e0));
@@ -1569,6 +1623,7 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
         if (rc || best.empty()) {
             b->block = keep_block;
             b->spt = keep_spt;
+            b->map = keep_map;
             batch_build_table(b);
             return rc ? rc : fail(LAT_EDEVICE, "batch autotune found no runnable shape");
         }
@@ -1576,6 +1631,7 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
     }
     b->block = best[0];
     b->spt = best[1];
+    b->map = best.size() > 2 && best[2] == 1 ? 1 : 0;
     b->tuned = true;
     int rc = batch_build_table(b);
     if (rc) return rc;
@@ -1583,6 +1639,14 @@ extern "C" int lat_batch_autotune(lat_batch_t b, int n_hb, int n_or, int result[
         result[0] = best[0];
         result[1] = best[1];
     }
+    return LAT_OK;
+}
+
+extern "C" int lat_batch_get_shape(lat_batch_t b, int shape[3]) {
+    if (!b || !shape) return fail(LAT_EINVAL, "NULL argument");
+    shape[0] = b->block;
+    shape[1] = b->spt;
+    shape[2] = b->map;
     return LAT_OK;
 }
 
@@ -1623,6 +1687,7 @@ extern "C" int lat_batch_destroy(lat_batch_t b) {
     if (b->d_lats) discard(hipFree(b->d_lats));
     if (b->d_counters) discard(hipFree(b->d_counters));
     if (b->d_work) discard(hipFree(b->d_work));
+    if (b->d_items) discard(hipFree(b->d_items));
     if (b->own_stream && b->stream) discard(hipStreamDestroy(b->stream));
     delete b;
     return LAT_OK;

@@ -1068,8 +1068,23 @@ LAT_DEV int batch_member(const BatchArgs& b, int r) {
     return lo;
 }
 
-// Runs tile `tile` of member `m` for pass gp (counted from the launch start).
-template <class ST3, class ST2>
+// The same with the pass kind, reunitarisation and (overrelaxation)
+// direction fixed at compile time, as the single-lattice passes are: the
+// kernel then needs only the registers of its own kind.
+template <class ST3, class ST2, int KIND, bool REUNIT, int MU>
+LAT_DEV void batch_site_fixed(const PassArgs& a, int64_t s) {
+    if (a.group == 3) {
+        if constexpr (KIND == 0) su3_site<ST3, 0, REUNIT, LAT_RNG_PHILOX_I>(a, s);
+        else su3_site<ST3, 1, REUNIT, LAT_RNG_CONST_I, MU>(a, s);
+    } else {
+        if constexpr (KIND == 0) su2_site<ST2, 0, REUNIT, LAT_RNG_PHILOX_I>(a, s);
+        else su2_site<ST2, 1, REUNIT, LAT_RNG_CONST_I>(a, s);
+    }
+}
+
+// Runs tile `tile` of member `m` for pass gp (counted from the launch start);
+// KIND < 0: kind, reunitarisation and direction from gp at run time.
+template <class ST3, class ST2, int KIND = -1, bool REUNIT = false, int MU = -1>
 LAT_DEV void batch_tile(const BatchArgs& b, int m, int tile, int64_t gp) {
     const BatchLat& L = b.lats[m];
     const int sweep = (int)(gp / b.passes_per_sweep);
@@ -1102,15 +1117,20 @@ LAT_DEV void batch_tile(const BatchArgs& b, int m, int tile, int64_t gp) {
     a.reverse = 0;
     a.frozen = 0;
     const int64_t end = (int64_t)(tile + 1) * b.tile < L.g.vh ? (int64_t)(tile + 1) * b.tile : L.g.vh;
-    for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < end; s += blockDim.x)
-        batch_site<ST3, ST2>(a, kind, reunit, s);
+    for (int64_t s = (int64_t)tile * b.tile + threadIdx.x; s < end; s += blockDim.x) {
+        if constexpr (KIND < 0) batch_site<ST3, ST2>(a, kind, reunit, s);
+        else batch_site_fixed<ST3, ST2, KIND, REUNIT, MU>(a, s);
+    }
 }
 
-template <class ST3, class ST2>
+// One launch per pass: work-group b takes the (member, tile) the host's map
+// assigns it; the map gives each member to one XCD (work-group b runs on XCD
+// b mod 8), so a member's neighbour links stay in that XCD's L2.
+template <class ST3, class ST2, int KIND, bool REUNIT, int MU>
 __global__ void __launch_bounds__(256) batch_pass(BatchArgs b, int64_t gp) {
-    const int r = (int)blockIdx.x;
-    const int m = batch_member(b, r);
-    batch_tile<ST3, ST2>(b, m, r - b.lats[m].tile_prefix, gp);
+    const BatchItem it = b.items[blockIdx.x];
+    if (it.member < 0) return;
+    batch_tile<ST3, ST2, KIND, REUNIT, MU>(b, it.member, it.tile, gp);
 }
 
 template <class ST3, class ST2>
@@ -1359,8 +1379,28 @@ static void batch_launch_typed(const BatchArgs& b, int mode, int grid, int block
         return;
     }
     const int64_t npass = (int64_t)b.passes_per_sweep * b.n_sweeps;
-    for (int64_t gp = 0; gp < npass; ++gp)
-        hipLaunchKernelGGL((batch_pass<ST3, ST2>), dim3(b.tiles_per_pass), dim3(block), 0, st, b, gp);
+    for (int64_t gp = 0; gp < npass; ++gp) {
+        // pass gp of the launch: the same decomposition as batch_tile's
+        const int pp = (int)(gp % b.passes_per_sweep);
+        const int sw = pp >> 3, mu = (pp >> 1) & 3;
+        const bool hb = sw < b.n_hb, re = (sw == b.n_hb + b.n_or - 1);
+        const dim3 g(b.nitems), t(block);
+        if (hb) {
+            if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 0, true, -1>), g, t, 0, st, b, gp);
+            else hipLaunchKernelGGL((batch_pass<ST3, ST2, 0, false, -1>), g, t, 0, st, b, gp);
+        } else {
+#define LAT_BATCH_OR(M)                                                                          \
+    if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, true, M>), g, t, 0, st, b, gp);          \
+    else hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, false, M>), g, t, 0, st, b, gp);
+            switch (mu) {
+                case 0: LAT_BATCH_OR(0) break;
+                case 1: LAT_BATCH_OR(1) break;
+                case 2: LAT_BATCH_OR(2) break;
+                default: LAT_BATCH_OR(3) break;
+            }
+#undef LAT_BATCH_OR
+        }
+    }
 }
 
 hipError_t lat_launch_batch(int storage, int mode, const BatchArgs& b, uint64_t** counters, int grid, int block,

@@ -82,6 +82,12 @@ struct BatchLat {
     int tile_prefix;  // index of this lattice's first tile within a pass
 };
 
+// One work-group's share of a batch pass: tile `tile` of member `member`
+// (member < 0: nothing, the work-group leaves at once).
+struct BatchItem {
+    int member, tile;
+};
+
 // Work list of one persistent batch launch: n_sweeps compound sweeps
 // (n_hb, n_or) of every member; item = (pass, lattice, tile), pass-major.
 struct BatchArgs {
@@ -95,4 +101,6 @@ struct BatchArgs {
     unsigned* done;       // [nlat] tiles completed in this launch
     int* status;          // nonzero if a dependency wait hit its spin limit
     unsigned spin_limit;
+    const BatchItem* items = nullptr;  // per-pass work-group -> (member, tile) map (one launch per pass)
+    int nitems = 0;                    // work-groups of a pass launch
 };

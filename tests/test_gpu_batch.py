@@ -28,7 +28,7 @@ def small_batch():
 
 
 @pytest.mark.parametrize("storage", [P.F32, P.F64, P.F32_C12, P.F64_C12])
-@pytest.mark.parametrize("shape", [(0, 256, 1, 0), (0, 64, 1, 0), (0, 128, 3, 0)])
+@pytest.mark.parametrize("shape", [(0, 256, 1, 0), (0, 64, 1, 0), (0, 128, 3, 0), (2, 128, 1, 0), (2, 64, 2, 0)])
 def test_members_equal_single_runs(storage, shape):
     descs = small_batch()
     b = P.Batch(descs, storage=storage, rng=P.RNG_PHILOX)
