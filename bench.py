@@ -11,13 +11,14 @@ FP64 18-real form gives the headline value.  Each form first picks its
 launch shape with the library's autotuner (the lattice state is restored).
 
 Also reported: the FP32, 12-real FP32 and 12-real FP64 storage forms
-(speed-up over FP64 and the difference of their observables from FP64), the
-roofline of the dominant pass kernel (event-timed in this run), SU(3)
-64^3 x 16 (the case that does not fit the last-level cache), the 64-lattice
-batch in FP32 against the same lattices run one by one in FP64, the paper's
-own Table 1 working sweeps (SU(3) 32^4, SU(2) 44^4, and the O(4) model on
-16^4 .. 72^4; its 2011 figures as context), and the FP64 CPU oracle timed on a bounded sample of the headline
-workload on the host cores.
+(speed-up over FP64), the precision of the FP32 forms against FP64 for every
+observable (paired runs that share start and random numbers), the roofline
+of the dominant pass kernel (event-timed in this run), SU(3) 64^3 x 16 (the
+case that does not fit the last-level cache), the 64-lattice batch in FP32
+against the same lattices run one by one in FP64, RANLUX-driven working
+sweeps on the lattice shapes of the paper's Table 1 (SU(3) 32^4, SU(2)
+44^4), the O(4) model's pass, and the FP64 CPU oracle timed on a bounded
+sample of the headline workload on the host cores.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -95,8 +96,9 @@ def run_form(P, form: str, steps: int, warmup: int):
     log(f"[{form}] warmup {warmup} steps")
     early, _ = lat.run(warmup, N_HB, N_OR, measure_every=1)
     # launch shape tuned on the warmed-up links (the state is restored)
-    shape = lat.autotune(N_HB, N_OR)
-    log(f"[{form}] launch shape {shape}")
+    lat.autotune(N_HB, N_OR)
+    shape = lat.launch_shapes()
+    log(f"[{form}] launch shapes {shape}")
     lat.run(1, N_HB, N_OR, measure_every=1)  # graph capture of the tuned shape
     torch.cuda.synchronize()
     log(f"[{form}] timing {steps} steps in {REPEATS} repeats")
@@ -140,28 +142,70 @@ def run_form(P, form: str, steps: int, warmup: int):
     return res
 
 
-def precision_study(P, steps: int, therm: int = 200):
-    """Long runs of every storage form on the headline lattice from the same
-    cold start and random numbers; the difference of each observable's mean
-    from the FP64 one, with binned errors (the chains decorrelate after a few
-    sweeps, so this bounds the precision forms' systematic error)."""
+def paired(x, y, nbins=50):
+    """Mean and binned error of the per-sweep difference x - y of two series
+    of the same length."""
     import numpy as np
-    out = {"steps": steps, "thermalisation": therm}
-    obs = {}
-    for form in ("f64", "f32", "f32c12", "f64c12"):
-        lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=3, start=P.COLD)
-        lat.run(therm, N_HB, N_OR, measure_every=0)
-        lat.autotune(N_HB, N_OR)
-        plaq, poly = lat.run(steps, N_HB, N_OR, measure_every=1)
-        lat.close()
-        series = {"P": plaq[:, 0], "P_s": plaq[:, 1], "P_t": plaq[:, 2], "ReL": poly[:, 0],
-                  "absL": np.hypot(poly[:, 0], poly[:, 1])}
-        obs[form] = {k: binned(v, 50) for k, v in series.items()}
-        log(f"[precision] {form}: <P> = {obs[form]['P'][0]:.7f} +- {obs[form]['P'][1]:.1e}")
-    out["means"] = {f: {k: {"mean": m, "err": e} for k, (m, e) in o.items()} for f, o in obs.items()}
-    out["delta_vs_f64"] = {f: {k: {"delta": obs[f][k][0] - obs["f64"][k][0],
-                                   "err": math.hypot(obs[f][k][1], obs["f64"][k][1])} for k in obs[f]}
-                           for f in obs if f != "f64"}
+    return binned(np.asarray(x) - np.asarray(y), nbins)
+
+
+def precision_leg(P, steps: int, therm: int = 200, forms=("f32c12", "f32", "f64c12"), seeds=(3,)):
+    """FP32 storage forms against FP64 on the headline lattice.  Within a
+    replica every form starts from the same cold links and draws the same
+    random numbers, so the chains are coupled and the per-sweep difference of
+    each observable (P, P_s, P_t, Re L, |L|) has a smaller variance than two
+    independent chains would give; its mean over `steps` measured compound
+    sweeps, after `therm` discarded ones, with a binned error (50 bins),
+    bounds the FP32 form's systematic error.  Replicas (one per seed) are
+    independent; their differences are combined as an inverse-variance
+    weighted mean, and the chi^2 of the replicas about it checks the binned
+    errors.  The independent-chain error is reported beside the paired one.
+    The FP64 12-real form, which rounds like the reference, is the control:
+    its difference shows what the decorrelation of coupled chains alone
+    gives."""
+    import numpy as np
+    out = {"steps": steps, "thermalisation": therm, "bins": 50, "bound": 1e-5, "seeds": list(seeds)}
+    keys = ("P", "P_s", "P_t", "ReL", "absL")
+    reps = []
+    for seed in seeds:
+        series = {}
+        for form in ("f64",) + tuple(forms):
+            t0 = time.perf_counter()
+            lat = P.Lattice(3, DIMS, BETA, FLUX, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=seed,
+                            start=P.COLD)
+            plaq, poly = lat.run(therm + steps, N_HB, N_OR, measure_every=1)
+            lat.close()
+            series[form] = {"P": plaq[therm:, 0], "P_s": plaq[therm:, 1], "P_t": plaq[therm:, 2],
+                            "ReL": poly[therm:, 0], "absL": np.hypot(poly[therm:, 0], poly[therm:, 1])}
+            log(f"[precision] seed {seed} {form}: {therm + steps} compound sweeps in "
+                f"{time.perf_counter() - t0:.1f} s")
+        ref = series["f64"]
+        rep = {"seed": seed, "f64_means": {k: dict(zip(("mean", "err"), binned(v, 50))) for k, v in ref.items()}}
+        for form in forms:
+            rows = {}
+            for k in keys:
+                v = series[form][k]
+                d, e = paired(v, ref[k])
+                rows[k] = {"delta": d, "err": e,
+                           "independent_chain_err": math.hypot(binned(v, 50)[1], binned(ref[k], 50)[1])}
+            rep[form] = rows
+            log(f"[precision] seed {seed} {form} - f64: <P> {rows['P']['delta']:.2e} +- {rows['P']['err']:.1e} "
+                f"(independent chains: +- {rows['P']['independent_chain_err']:.1e})")
+        reps.append(rep)
+    out["replicas"] = reps
+    for form in forms:
+        comb = {}
+        for k in keys:
+            d = np.array([r[form][k]["delta"] for r in reps])
+            e = np.array([r[form][k]["err"] for r in reps])
+            w = 1.0 / e ** 2
+            m = float(np.sum(w * d) / np.sum(w))
+            comb[k] = {"delta": m, "err": float(np.sqrt(1.0 / np.sum(w))),
+                       "chi2_per_dof": float(np.sum(w * (d - m) ** 2) / (len(d) - 1)) if len(d) > 1 else None}
+        dp = comb["P"]
+        comb["P_within_bound"] = bool(abs(dp["delta"]) + 2 * dp["err"] <= out["bound"])
+        out[form] = comb
+        log(f"[precision] {form} - f64 over {len(seeds)} replica(s): <P> {dp['delta']:.2e} +- {dp['err']:.1e}")
     return out
 
 
@@ -174,7 +218,8 @@ def run_large(P, sweeps: int = 40):
     for form in ("f64", "f32c12"):
         lat = P.Lattice(3, dims, 6.0, 0, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=23, start=P.HOT)
         lat.run(5, N_HB, N_OR, measure_every=0)
-        shape = lat.autotune(N_HB, N_OR)
+        lat.autotune(N_HB, N_OR)
+        shape = lat.launch_shapes()
         lat.run(1, N_HB, N_OR, measure_every=1)  # graph capture
         t0 = time.perf_counter()
         plaq, _ = lat.run(sweeps, N_HB, N_OR, measure_every=1)
@@ -251,8 +296,8 @@ def run_batch(P, sweeps: int = 10, precision_sweeps: int = 1000):
 def batch_precision(P, descs, n, therm=100):
     """<P> of every member, FP32 batch against FP64 batch: the same Haar
     starts and random numbers, `n` compound sweeps, the first `therm`
-    discarded.  The chains decorrelate, so the members' differences are
-    combined as a weighted mean with its error."""
+    discarded.  Each member's per-sweep difference gives a paired mean and
+    binned error; the members' differences are combined as a weighted mean."""
     import numpy as np
     series = {}
     for name, storage in (("f32", P.F32), ("f64", P.F64)):
@@ -266,9 +311,9 @@ def batch_precision(P, descs, n, therm=100):
         series[name] = ps
     delta, err = [], []
     for i in range(len(descs)):
-        (mb, eb), (ms, es) = binned(series["f32"][therm:, i]), binned(series["f64"][therm:, i])
-        delta.append(mb - ms)
-        err.append(math.hypot(eb, es))
+        d, e = paired(series["f32"][therm:, i], series["f64"][therm:, i], 10)
+        delta.append(d)
+        err.append(e)
     delta, err = np.array(delta), np.array(err)
     w = 1.0 / err ** 2
     dw = float(np.sum(w * delta) / np.sum(w))
@@ -276,7 +321,8 @@ def batch_precision(P, descs, n, therm=100):
     log(f"[batch] weighted <P> difference FP32 - FP64 {dw:.2e} +- {ew:.1e}")
     return {"sweeps": n, "thermalisation": therm, "weighted_mean_delta_P": dw, "weighted_mean_delta_P_err": ew,
             "chi2_per_member": float(np.mean((delta / err) ** 2)),
-            "max_abs_member_delta_P": float(np.max(np.abs(delta)))}
+            "max_abs_member_delta_P": float(np.max(np.abs(delta))),
+            "P_within_bound": bool(abs(dw) + 2 * ew <= 1e-5)}
 
 
 def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
@@ -307,38 +353,31 @@ def cpu_model() -> str:
     return "unknown"
 
 
-# The paper's Table 1 working sweeps (one heat-bath sweep with NHIT = 10 and
-# reunitarisation, plus the measurement; Haar start; RANLUX luxury level 3
-# streams as in the paper, Philox beside them), with the link-update rates
-# derived from its seconds per sweep on its own 2011 GPUs: context only.
-PAPER_TABLE1 = [
-    {"group": 3, "dims": (32, 32, 32, 32), "beta": 6.0,
-     "paper": {"device": "GeForce GTX 560 Ti (OpenCL)", "f32": 7.49e6, "f64": 3.58e6}},
-    {"group": 2, "dims": (44, 44, 44, 44), "beta": 2.3,
-     "paper": {"device": "GeForce GTX 560 Ti (OpenCL)", "f32": 1.58e7, "f64": 1.32e7}},
-]
+# Working sweeps (one heat-bath sweep with NHIT = 10 and reunitarisation,
+# plus the measurement; Haar start) on the lattice shapes of the paper's
+# Table 1, with RANLUX luxury-level-3 streams (the paper's generator) and
+# Philox beside them.
+TABLE1_SHAPES = [{"group": 3, "dims": (32, 32, 32, 32), "beta": 6.0},
+                 {"group": 2, "dims": (44, 44, 44, 44), "beta": 2.3}]
 
 
-def run_paper_workloads(P, sweeps: int = 20):
+def run_ranlux_workloads(P, sweeps: int = 20):
     out = []
-    for w in PAPER_TABLE1:
+    for w in TABLE1_SHAPES:
         V = volume(w["dims"])
-        row = {"group": w["group"], "lattice": list(w["dims"]), "beta": w["beta"], "paper": w["paper"]}
+        row = {"group": w["group"], "lattice": list(w["dims"]), "beta": w["beta"]}
         for form, storage in (("f64", P.F64), ("f32", P.F32)):
             rates = {}
             for gen, rng in (("ranlux", P.RNG_RANLUX), ("philox", P.RNG_PHILOX)):
                 lat = P.Lattice(w["group"], w["dims"], w["beta"], 0, storage=storage, rng=rng, seed=5,
                                 start=P.HOT)
-                lat.run(3, 1, 0, measure_every=1)
-                lat.autotune(1, 0)
-                lat.run(1, 1, 0, measure_every=1)  # graph capture of the tuned shape
+                lat.run(3, 1, 0, measure_every=1)  # includes the graph capture
                 t0 = time.perf_counter()
                 lat.run(sweeps, 1, 0, measure_every=1)
                 rates[gen] = sweeps * 4 * V / (time.perf_counter() - t0)
                 lat.close()
-            row[form] = {"link_updates_per_s": rates["ranlux"], "ratio_to_paper": rates["ranlux"] / w["paper"][form],
-                         "philox_link_updates_per_s": rates["philox"]}
-        log(f"[paper table 1] SU({w['group']}) {w['dims']} RANLUX: F64 {row['f64']['link_updates_per_s']:.3e}, "
+            row[form] = {"link_updates_per_s": rates["ranlux"], "philox_link_updates_per_s": rates["philox"]}
+        log(f"[RANLUX working sweeps] SU({w['group']}) {w['dims']}: F64 {row['f64']['link_updates_per_s']:.3e}, "
             f"F32 {row['f32']['link_updates_per_s']:.3e} link updates/s")
         out.append(row)
     return out
@@ -349,14 +388,7 @@ def run_paper_workloads(P, sweeps: int = 20):
 # model's coupling space (the paper gives none; delta gives about the 50%
 # acceptance the paper mentions).
 O4_KAPPA, O4_LAMBDA, O4_DELTA, O4_NHIT = 0.3, 1.0, 0.55, 100
-# Seconds per working sweep of its fastest single-device run per lattice (SP, DP).
-PAPER_TABLE1_O4 = [
-    {"L": 16, "paper": {"device": "GeForce GTX 560M", "f32": 0.08, "f64": 0.12}},
-    {"L": 24, "paper": {"device": "GeForce GTX 560M", "f32": 0.42, "f64": 0.6}},
-    {"L": 32, "paper": {"device": "Radeon HD 7970 (2 parts)", "f32": 0.66, "f64": 0.95}},
-    {"L": 48, "paper": {"device": "GeForce GTX 560 Ti (4 parts)", "f32": 4.64, "f64": 6.10}},
-    {"L": 72, "paper": {"device": "Radeon HD 7970 (12 parts)", "f32": 20.35, "f64": 36.2}},
-]
+O4_SIZES = (16, 32, 72)
 O4_SOURCES = ["paper_1310_7087_amd/csrc/lat_on.hip", "paper_1310_7087_amd/csrc/lat_dev.hpp",
               "paper_1310_7087_amd/csrc/lat_types.hpp"]
 # one wave64 VALU instruction per compute unit and cycle (4 SIMDs of 16
@@ -381,17 +413,14 @@ def o4_valu_per_hit():
     return data.get("valu_wave_instructions_per_hit")
 
 
-def run_o4(P, sweeps: int = 10, sizes=None):
-    """The paper's Table 1 O(4) lattices: working sweeps (sweep + measurement)
+def run_o4(P, sweeps: int = 10, sizes=O4_SIZES):
+    """The O(4) model on L^4 lattices: working sweeps (sweep + measurement)
     with RANLUX (the paper's generator) and Philox, FP64 and FP32 storage."""
     out = []
-    for w in PAPER_TABLE1_O4:
-        if sizes and w["L"] not in sizes:
-            continue
-        dims = (w["L"],) * 4
+    for L in sizes:
+        dims = (L,) * 4
         V = volume(dims)
-        row = {"lattice": list(dims), "kappa": O4_KAPPA, "lambda": O4_LAMBDA, "delta": O4_DELTA, "nhit": O4_NHIT,
-               "paper_seconds_per_working_sweep": w["paper"]}
+        row = {"lattice": list(dims), "kappa": O4_KAPPA, "lambda": O4_LAMBDA, "delta": O4_DELTA, "nhit": O4_NHIT}
         for form, st in (("f64", P.F64), ("f32", P.F32)):
             for gen, rng in (("ranlux", P.RNG_RANLUX), ("philox", P.RNG_PHILOX)):
                 f = P.ONField(4, dims, O4_KAPPA, O4_LAMBDA, 0.0, O4_DELTA, storage=st, rng=rng, seed=5,
@@ -401,10 +430,9 @@ def run_o4(P, sweeps: int = 10, sizes=None):
                 f.run(sweeps, 1)
                 dt = (time.perf_counter() - t0) / sweeps
                 row[f"{form}_{gen}"] = {"seconds_per_working_sweep": dt, "site_updates_per_s": V / dt,
-                                        "hits_per_s": V * O4_NHIT / dt, "acceptance": f.acceptance(),
-                                        "speedup_vs_paper": w["paper"][form] / dt}
+                                        "hits_per_s": V * O4_NHIT / dt, "acceptance": f.acceptance()}
                 f.close()
-        log(f"[O(4) {w['L']}^4] F64 RANLUX {row['f64_ranlux']['seconds_per_working_sweep'] * 1e3:.2f} ms, "
+        log(f"[O(4) {L}^4] F64 RANLUX {row['f64_ranlux']['seconds_per_working_sweep'] * 1e3:.2f} ms, "
             f"Philox {row['f64_philox']['seconds_per_working_sweep'] * 1e3:.2f} ms per working sweep")
         out.append(row)
     # the pass kernel's VALU issue rate at 32^4 (FP64, Philox)
@@ -422,7 +450,7 @@ def run_o4(P, sweeps: int = 10, sizes=None):
     if per_hit:
         roof["achieved"] = hits * per_hit / (ms * 1e-3)
         roof["frac"] = roof["achieved"] / VALU_WAVE_INSTR_PEAK
-    return {"table1": out, "o4_32_pass_roofline": roof}
+    return {"lattices": out, "o4_32_pass_roofline": roof}
 
 
 def cpu_baseline(steps: int):
@@ -454,8 +482,10 @@ def cpu_baseline(steps: int):
 
 
 def traffic_for(kernel: str, form: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, valid
-    only while the kernel sources are unchanged since it was taken."""
+    """Bytes per launch between the L2 caches and the memory fabric (reads
+    plus writes; they are served by HBM or by the last-level cache in front
+    of it) from the committed rocprofv3 PMC summary, valid only while the
+    kernel sources are unchanged since it was taken."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -467,7 +497,7 @@ def traffic_for(kernel: str, form: str):
     if data.get("kernel_hash") != kernel_hash():
         return None
     entry = data.get("kernels", {}).get(f"{form}:{kernel}")
-    return None if entry is None else entry.get("hbm_bytes_per_launch")
+    return None if entry is None else entry.get("fabric_bytes_per_launch")
 
 
 def main() -> int:
@@ -481,17 +511,23 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the 64^3x16 and batch measurements")
     ap.add_argument("--precision-sweeps", type=int, default=1000,
                     help="compound sweeps of the batch precision comparison (0 skips it)")
-    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
-                    help="only run the long FP32/12-real vs FP64 comparison of every observable "
-                         "(STEPS measured steps per form) and print its JSON line")
+    ap.add_argument("--precision-steps", type=int, default=20000,
+                    help="measured compound sweeps per form of the paired FP32-vs-FP64 precision leg "
+                         "(0 skips it)")
+    ap.add_argument("--precision-forms", default="f32c12,f32,f64c12",
+                    help="storage forms compared with FP64 in the precision leg")
+    ap.add_argument("--precision-seeds", default="3",
+                    help="seeds of the independent replicas of the precision leg")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only run the precision leg and print its JSON line")
     ap.add_argument("--cpu-steps", type=int, default=8,
                     help="steps of the CPU oracle in the bounded baseline sample (about 1 s each on 16 cores)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size kernel that "
                          "calibrates the profiler's HBM byte counters)")
     ap.add_argument("--o4-only", action="store_true",
-                    help="only run the O(4) model's Table 1 lattices and print their JSON line")
-    ap.add_argument("--o4-sizes", default="16,24,32,48,72", help="O(4) lattice extents L (L^4) to run")
+                    help="only run the O(4) model's lattices and print their JSON line")
+    ap.add_argument("--o4-sizes", default="16,32,72", help="O(4) lattice extents L (L^4) to run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice is resident on a single MI355X); "
@@ -503,14 +539,16 @@ def main() -> int:
         return 1
     import paper_1310_7087_amd as P
 
-    if args.precision_study > 0:
-        print(json.dumps({"precision_study": precision_study(P, args.precision_study),
+    seeds = tuple(int(x) for x in args.precision_seeds.split(",") if x.strip())
+    pforms = tuple(x.strip() for x in args.precision_forms.split(",") if x.strip())
+    if args.precision_only:
+        print(json.dumps({"precision": precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds),
                           "workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or"}), flush=True)
         return 0
 
+    o4_sizes = tuple(int(x) for x in args.o4_sizes.split(",") if x.strip())
     if args.o4_only:
-        sizes = {int(x) for x in args.o4_sizes.split(",") if x.strip()}
-        print(json.dumps({"o4_paper_table1": run_o4(P, sizes=sizes)}), flush=True)
+        print(json.dumps({"o4": run_o4(P, sizes=o4_sizes)}), flush=True)
         return 0
 
     if args.copy_mib > 0:
@@ -537,9 +575,13 @@ def main() -> int:
     kname = "or_pass" if share_or >= share_hb else "hb_pass"
     t_us = r[kname + "_us"]
     achieved = r["pass_bytes"] / (t_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"su3_pass<{head},{'overrelax' if kname == 'or_pass' else 'heatbath'}>",
+    kshape = r["launch_shape"]["overrelaxation" if kname == "or_pass" else "heat_bath"]
+    kfn = "su3_pass_lq" if kshape["stage_lds"] else "su3_pass"
+    roofline = {"bound": "hbm", "kernel": f"{kfn}<{head},{'overrelax' if kname == 'or_pass' else 'heatbath'}>",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic_for(kname, head), "avg_launch_us": t_us,
+                "traffic": traffic_for(kname, head),
+                "traffic_kind": "L2-to-fabric bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
+                "avg_launch_us": t_us,
                 "algorithmic_bytes_per_launch": r["pass_bytes"]}
     out = {
         "metric": "SU(3) link updates/s at 32^3x8 HB+OR",
@@ -563,25 +605,21 @@ def main() -> int:
         "forms": {f: {k: v for k, v in results[f].items() if k != "pass_bytes"} for f in forms},
     }
     if "f64" in results:
-        ref = results["f64"]["observables"]
         for f in forms:
             if f != "f64":
                 fr = out["forms"][f]
                 fr["speedup_vs_f64"] = results[f]["link_updates_per_s"] / results["f64"]["link_updates_per_s"]
-                # difference of each observable's long-run mean from the FP64 one
-                # (the chains decorrelate, so it is a statistical comparison)
                 # the same start and random numbers: the first sweeps track the
-                # FP64 trajectory until the chains decorrelate
+                # FP64 trajectory until rounding differences grow
                 fr["early_abs_delta_P_vs_f64"] = [
                     abs(a - b) for a, b in zip(results[f]["early_plaquettes"], results["f64"]["early_plaquettes"])]
-                fr["delta_vs_f64"] = {
-                    k: {"delta": v["mean"] - ref[k]["mean"], "err": math.hypot(v["err"], ref[k]["err"])}
-                    for k, v in results[f]["observables"].items()}
+    if args.precision_steps > 0:
+        out["precision"] = precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds)
     if not args.no_extras:
         out["su3_64x16"] = run_large(P)
         out["batch_64_lattices"] = run_batch(P, precision_sweeps=args.precision_sweeps)
-        out["paper_table1_workloads"] = run_paper_workloads(P)
-        out["o4_paper_table1"] = run_o4(P)
+        out["ranlux_working_sweeps"] = run_ranlux_workloads(P)
+        out["o4"] = run_o4(P, sizes=o4_sizes)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)

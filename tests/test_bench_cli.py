@@ -34,7 +34,7 @@ def test_committed_traffic_is_used_only_for_the_kernels_it_was_taken_on(tmp_path
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_hash", lambda: real)
     (tmp_path / "profiles").mkdir()
-    entry = {"kernels": {"f64:or_pass": {"hbm_bytes_per_launch": 1.5e8}}}
+    entry = {"kernels": {"f64:or_pass": {"fabric_bytes_per_launch": 1.5e8}}}
     (tmp_path / "profiles" / "pmc_traffic.json").write_text(json.dumps(dict(entry, kernel_hash=real)))
     assert bench.traffic_for("or_pass", "f64") == 1.5e8
     (tmp_path / "profiles" / "pmc_traffic.json").write_text(json.dumps(dict(entry, kernel_hash="0" * 16)))
