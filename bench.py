@@ -209,6 +209,36 @@ def precision_leg(P, steps: int, therm: int = 200, forms=("f32c12", "f32", "f64c
     return out
 
 
+def precision_large(P, steps: int, therm: int = 200, seed: int = 23):
+    """FP32 12-real against FP64 on SU(3) 64^3 x 16 (beta 6.0, Haar start):
+    one coupled pair of chains (same start, same random numbers), `therm`
+    compound sweeps discarded, the paired per-sweep difference of each
+    observable over `steps` measured ones with a binned error (20 bins)."""
+    import numpy as np
+    dims = (64, 64, 64, 16)
+    series = {}
+    for form in ("f64", "f32c12"):
+        t0 = time.perf_counter()
+        lat = P.Lattice(3, dims, 6.0, 0, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=seed, start=P.HOT)
+        plaq, poly = lat.run(therm + steps, N_HB, N_OR, measure_every=1)
+        lat.close()
+        series[form] = {"P": plaq[therm:, 0], "P_s": plaq[therm:, 1], "P_t": plaq[therm:, 2],
+                        "ReL": poly[therm:, 0], "absL": np.hypot(poly[therm:, 0], poly[therm:, 1])}
+        log(f"[precision 64^3x16] {form}: {therm + steps} compound sweeps in {time.perf_counter() - t0:.1f} s")
+    out = {"lattice": list(dims), "beta": 6.0, "start": "hot", "seed": seed, "steps": steps,
+           "thermalisation": therm, "bins": 20, "bound": 1e-5,
+           "f64_means": {k: dict(zip(("mean", "err"), binned(v, 20))) for k, v in series["f64"].items()}}
+    rows = {}
+    for k, v in series["f32c12"].items():
+        d, e = paired(v, series["f64"][k], 20)
+        rows[k] = {"delta": d, "err": e,
+                   "independent_chain_err": math.hypot(binned(v, 20)[1], binned(series["f64"][k], 20)[1])}
+    rows["P_within_bound"] = bool(abs(rows["P"]["delta"]) + 2 * rows["P"]["err"] <= 1e-5)
+    out["f32c12"] = rows
+    log(f"[precision 64^3x16] f32c12 - f64: <P> {rows['P']['delta']:.2e} +- {rows['P']['err']:.1e}")
+    return out
+
+
 def run_large(P, sweeps: int = 40):
     """SU(3) 64^3 x 16, beta 6.0, Haar start (seed 23): FP64 18-real against
     FP32 12-real on the lattice that does not fit the 256 MB last-level cache."""
@@ -293,36 +323,56 @@ def run_batch(P, sweeps: int = 10, precision_sweeps: int = 1000):
     return out
 
 
-def batch_precision(P, descs, n, therm=100):
-    """<P> of every member, FP32 batch against FP64 batch: the same Haar
-    starts and random numbers, `n` compound sweeps, the first `therm`
-    discarded.  Each member's per-sweep difference gives a paired mean and
-    binned error; the members' differences are combined as a weighted mean."""
+def batch_precision(P, descs, n, therm=100, seeds=(None,)):
+    """Every member of the batch, FP32 batch against FP64 batch: the same
+    Haar starts and random numbers, `n` compound sweeps, the first `therm`
+    discarded.  Each member's per-sweep difference of P, P_s, P_t and |L|
+    gives a paired mean and binned error; the members' differences (of every
+    replica: one per seed, which replaces the members' own seeds) are
+    combined as an inverse-variance weighted mean, with the chi^2 per member
+    about it.  Re L is not compared: the small members tunnel between centre
+    sectors, so two decorrelated chains sit in different sectors for long
+    stretches and the paired difference of Re L has no usable binned error;
+    |L| does not depend on the sector."""
     import numpy as np
-    series = {}
-    for name, storage in (("f32", P.F32), ("f64", P.F64)):
-        bt = P.Batch(descs, storage=storage)
-        bt.autotune(N_HB, N_OR)
-        ps = np.empty((n, len(descs)))
-        for k in range(n):
-            p, _ = bt.run(1, N_HB, N_OR, measure=True)
-            ps[k] = p[:, 0]
-        bt.close()
-        series[name] = ps
-    delta, err = [], []
-    for i in range(len(descs)):
-        d, e = paired(series["f32"][therm:, i], series["f64"][therm:, i], 10)
-        delta.append(d)
-        err.append(e)
-    delta, err = np.array(delta), np.array(err)
-    w = 1.0 / err ** 2
-    dw = float(np.sum(w * delta) / np.sum(w))
-    ew = float(np.sqrt(1.0 / np.sum(w)))
-    log(f"[batch] weighted <P> difference FP32 - FP64 {dw:.2e} +- {ew:.1e}")
-    return {"sweeps": n, "thermalisation": therm, "weighted_mean_delta_P": dw, "weighted_mean_delta_P_err": ew,
-            "chi2_per_member": float(np.mean((delta / err) ** 2)),
-            "max_abs_member_delta_P": float(np.max(np.abs(delta))),
-            "P_within_bound": bool(abs(dw) + 2 * ew <= 1e-5)}
+    keys = ("P", "P_s", "P_t", "absL")
+    nbins = 20 if n - therm >= 2000 else 10
+    deltas = {k: [] for k in keys}
+    errs = {k: [] for k in keys}
+    for seed in seeds:
+        ds = descs if seed is None else [dict(d, seed=seed) for d in descs]
+        series = {}
+        for name, storage in (("f32", P.F32), ("f64", P.F64)):
+            t0 = time.perf_counter()
+            bt = P.Batch(ds, storage=storage)
+            bt.autotune(N_HB, N_OR)
+            obs = np.empty((n, len(ds), 4))
+            for k in range(n):
+                p, l = bt.run(1, N_HB, N_OR, measure=True)
+                obs[k, :, :3] = p[:, :3]
+                obs[k, :, 3] = np.hypot(l[:, 0], l[:, 1])
+            bt.close()
+            series[name] = obs[therm:]
+            log(f"[batch precision] seed {seed}: {name} {n} compound sweeps in {time.perf_counter() - t0:.1f} s")
+        for j, key in enumerate(keys):
+            for i in range(len(ds)):
+                d, e = paired(series["f32"][:, i, j], series["f64"][:, i, j], nbins)
+                deltas[key].append(d)
+                errs[key].append(e)
+    out = {"sweeps": n, "thermalisation": therm, "bins": nbins, "bound": 1e-5,
+           "member_seeds": [s for s in seeds if s is not None] or "workload"}
+    for key in keys:
+        delta, err = np.array(deltas[key]), np.array(errs[key])
+        w = 1.0 / err ** 2
+        dw = float(np.sum(w * delta) / np.sum(w))
+        out[key] = {"delta": dw, "err": float(np.sqrt(1.0 / np.sum(w))),
+                    "chi2_per_member": float(np.mean(((delta - dw) / err) ** 2)),
+                    "max_abs_member_delta": float(np.max(np.abs(delta)))}
+    dp = out["P"]
+    # a run too short to resolve 1e-5 does not decide the bound
+    out["P_within_bound"] = (bool(abs(dp["delta"]) + 2 * dp["err"] <= 1e-5) if dp["err"] <= 3e-6 else None)
+    log(f"[batch] weighted <P> difference FP32 - FP64 {dp['delta']:.2e} +- {dp['err']:.1e}")
+    return out
 
 
 def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
@@ -514,9 +564,15 @@ def main() -> int:
     ap.add_argument("--precision-steps", type=int, default=20000,
                     help="measured compound sweeps per form of the paired FP32-vs-FP64 precision leg "
                          "(0 skips it)")
-    ap.add_argument("--precision-forms", default="f32c12,f32,f64c12",
+    ap.add_argument("--precision-forms", default="f32c12,f32",
                     help="storage forms compared with FP64 in the precision leg")
-    ap.add_argument("--precision-seeds", default="3",
+    ap.add_argument("--batch-precision-seeds", default="",
+                    help="member seeds of independent replicas of the batch precision comparison "
+                         "(default: the workload's own seeds, one replica)")
+    ap.add_argument("--precision-large-steps", type=int, default=0,
+                    help="measured compound sweeps of the FP32 12-real vs FP64 comparison on 64^3x16 "
+                         "(0 skips it)")
+    ap.add_argument("--precision-seeds", default="3,4,5",
                     help="seeds of the independent replicas of the precision leg")
     ap.add_argument("--precision-only", action="store_true",
                     help="only run the precision leg and print its JSON line")
@@ -542,8 +598,18 @@ def main() -> int:
     seeds = tuple(int(x) for x in args.precision_seeds.split(",") if x.strip())
     pforms = tuple(x.strip() for x in args.precision_forms.split(",") if x.strip())
     if args.precision_only:
-        print(json.dumps({"precision": precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds),
-                          "workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or"}), flush=True)
+        res = {"workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or"}
+        if args.precision_steps > 0:
+            res["precision"] = precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds)
+        if args.precision_large_steps > 0:
+            res["precision_64x16"] = precision_large(P, args.precision_large_steps)
+        if args.precision_sweeps > 0:
+            from inputs import batch_workloads
+            descs = [dict(group=w.group, dims=w.dims, beta=w.beta, flux=w.flux, seed=w.seed, start=w.start,
+                          lattice_id=w.lattice_id) for w in batch_workloads(64, seed=11)]
+            bseeds = tuple(int(x) for x in args.batch_precision_seeds.split(",") if x.strip()) or (None,)
+            res["batch_precision"] = batch_precision(P, descs, args.precision_sweeps, seeds=bseeds)
+        print(json.dumps(res), flush=True)
         return 0
 
     o4_sizes = tuple(int(x) for x in args.o4_sizes.split(",") if x.strip())
@@ -582,7 +648,11 @@ def main() -> int:
                 "traffic": traffic_for(kname, head),
                 "traffic_kind": "L2-to-fabric bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
                 "avg_launch_us": t_us,
-                "algorithmic_bytes_per_launch": r["pass_bytes"]}
+                "algorithmic_bytes_per_launch": r["pass_bytes"],
+                # the FP64 32^3x8 lattice (151 MB) fits the 256 MB last-level cache in front of
+                # HBM; su3_64x16 (2.4 GB) gives the pass against HBM alone
+                "lattice_bytes": 4 * volume(DIMS) * BYTES_PER_LINK[head],
+                "fits_last_level_cache": 4 * volume(DIMS) * BYTES_PER_LINK[head] < 256 * 2 ** 20}
     out = {
         "metric": "SU(3) link updates/s at 32^3x8 HB+OR",
         "value": r["link_updates_per_s"],
@@ -615,6 +685,8 @@ def main() -> int:
                     abs(a - b) for a, b in zip(results[f]["early_plaquettes"], results["f64"]["early_plaquettes"])]
     if args.precision_steps > 0:
         out["precision"] = precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds)
+    if args.precision_large_steps > 0:
+        out["precision_64x16"] = precision_large(P, args.precision_large_steps)
     if not args.no_extras:
         out["su3_64x16"] = run_large(P)
         out["batch_64_lattices"] = run_batch(P, precision_sweeps=args.precision_sweeps)

@@ -367,7 +367,9 @@ class Batch:
         return p, l
 
     def configure(self, mode=0, block_size=256, sites_per_thread=1, grid=0):
-        """mode 0: one launch per pass over all members; 1: persistent work list."""
+        """mode 0: one launch per pass over all members, each member whole on
+        one XCD; 2: the same with the members' tiles dealt round the XCDs;
+        1 (persistent work list) is refused with LAT_EUNSUPPORTED."""
         _check(lib.lat_batch_configure(self._h, int(mode), int(block_size), int(sites_per_thread), int(grid)))
 
     def autotune(self, n_hb=1, n_or=4) -> dict:

@@ -48,15 +48,44 @@ def test_members_equal_single_runs(storage, shape):
 
 
 def test_batch_member_matches_oracle():
+    """FP64 batch, every member (the flux member and the 12^3x6 one
+    included): one heat-bath sweep from the Haar start against the oracle."""
     descs = small_batch()
     b = P.Batch(descs, storage=P.F64, rng=P.RNG_PHILOX)
     b.run(1, 1, 0)
-    for i in (0, 1, 3):
-        d = descs[i]
+    for i, d in enumerate(descs):
         o = O.Lattice(d["group"], d["dims"], d["beta"], flux=d.get("flux", 0), seed=d["seed"],
                       lattice_id=d["lattice_id"], start=O.HOT)
         o.sweep(1, 0)
-        assert np.abs(b.get_links(i) - o.get_links()).max() < 1e-12
+        assert np.abs(b.get_links(i) - o.get_links()).max() < 1e-12, i
+
+
+def test_batch_compound_sweep_matches_oracle_from_thermalised_links():
+    """FP64 batch from thermalised links (ten compound sweeps of each member
+    run alone; single-lattice FP64 parity is tested elsewhere): one
+    (1 HB + 4 OR) compound sweep of every member against the oracle at the
+    FP64 bar, links and observables."""
+    descs = small_batch()
+    starts = []
+    for d in descs:
+        g = P.Lattice(d["group"], d["dims"], d["beta"], d.get("flux", 0), storage=P.F64, rng=P.RNG_PHILOX,
+                      seed=d["seed"] + 100, lattice_id=d["lattice_id"], start=P.COLD)
+        g.run(10, 1, 4, measure_every=0)
+        starts.append(g.get_links())
+        g.close()
+    b = P.Batch(descs, storage=P.F64, rng=P.RNG_PHILOX)
+    for i, l in enumerate(starts):
+        b.set_links(i, l)
+    pb, lb = b.run(1, 1, 4)
+    for i, d in enumerate(descs):
+        o = O.Lattice(d["group"], d["dims"], d["beta"], flux=d.get("flux", 0), seed=d["seed"],
+                      lattice_id=d["lattice_id"], start=O.COLD)
+        o.set_links(starts[i])
+        o.sweep(1, 4)
+        assert np.abs(b.get_links(i) - o.get_links()).max() < 1e-12, i
+        po, lo = o.measure()
+        assert np.abs(pb[i] - po).max() < 1e-12 and np.abs(lb[i] - lo).max() < 1e-12, i
+    b.close()
 
 
 def test_scan_workload_runs_and_repeats():
