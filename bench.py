@@ -142,6 +142,29 @@ def run_form(P, form: str, steps: int, warmup: int):
     return res
 
 
+def run_flux_observables(P, forms, steps: int = 1000, warmup: int = 50, fluxes=(0, 4)):
+    """The headline lattice at the other flux quanta of the workload (n = 0
+    and 4; n = 1 is the timed run): P, P_s, P_t, Re L and |L| with binned
+    errors per storage form, from the cold start, `warmup` compound sweeps
+    discarded.  The background is a change of variables of the Haar measure,
+    so the equilibrium values do not depend on n."""
+    import numpy as np
+    out = {}
+    for n in fluxes:
+        row = {}
+        for form in forms:
+            lat = P.Lattice(3, DIMS, BETA, n, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=3, start=P.COLD)
+            lat.run(warmup, N_HB, N_OR, measure_every=0)
+            lat.autotune(N_HB, N_OR)
+            plaq, poly = lat.run(steps, N_HB, N_OR, measure_every=1)
+            lat.close()
+            row[form] = observables(plaq, poly)
+        out[f"flux_{n}"] = row
+        log(f"[flux {n}] <P> " + ", ".join(f"{f} {row[f]['P']['mean']:.6f}({row[f]['P']['err'] * 1e6:.0f}e-6)"
+                                           for f in forms))
+    return out
+
+
 def paired(x, y, nbins=50):
     """Mean and binned error of the per-sweep difference x - y of two series
     of the same length."""
@@ -589,6 +612,15 @@ def main() -> int:
         print(f"bench.py measures one GPU only (the lattice is resident on a single MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
+    if "LAT_TUNE_CACHE" not in os.environ:
+        # launch shapes tuned once per lattice shape and reused by the later legs
+        import atexit
+        import tempfile
+        fd, path = tempfile.mkstemp(prefix="lat_tune_", suffix=".json")
+        os.close(fd)
+        os.remove(path)
+        os.environ["LAT_TUNE_CACHE"] = path
+        atexit.register(lambda: os.path.exists(path) and os.remove(path))
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -683,6 +715,10 @@ def main() -> int:
                 # FP64 trajectory until rounding differences grow
                 fr["early_abs_delta_P_vs_f64"] = [
                     abs(a - b) for a, b in zip(results[f]["early_plaquettes"], results["f64"]["early_plaquettes"])]
+    if not args.no_extras:
+        flux = run_flux_observables(P, forms)
+        flux["flux_1"] = {f: results[f]["observables"] for f in forms}
+        out["observables_by_flux"] = flux
     if args.precision_steps > 0:
         out["precision"] = precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds)
     if args.precision_large_steps > 0:
