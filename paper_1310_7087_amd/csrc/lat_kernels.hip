@@ -387,31 +387,49 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site(
     for (int g = 0; g < 3; ++g) {
         const int ia = SUB_A[g], ib = SUB_B[g];
         const qt<T> qb = block_quat(W, ia, ib);
-        const qt<double> qd = {(double)qb.q0, (double)qb.q1, (double)qb.q2, (double)qb.q3};
-        const double k = sqrt(qnorm2(qd));
-        qt<double> r;
-        if constexpr (KIND == 0) {
-            const double alpha = 2.0 * a.beta * k / 3.0;
-            int8_t* log = a.accept_log ? a.accept_log + ((((int64_t)a.hb_offset * 4 + mu) * (2 * a.g.vh) + canon) * 3 + g) : nullptr;
-            if (!(alpha >= 1e-12)) {
-                if (log) *log = -1;
-                continue;
-            }
-            qt<double> x;
-            int t;
-            if constexpr (PREPARE) t = kp_prepared(alpha, a.nhit, d, g, first[g], x);
-            else t = kp(alpha, a.nhit, d, g, x);
-            if (log) *log = (int8_t)t;
-            if (t < 0) continue;
-            const double ik = 1.0 / k;
-            r = qmul_na(x, qt<double>{qd.q0 * ik, qd.q1 * ik, qd.q2 * ik, qd.q3 * ik});
+        qt<T> rt;
+        if constexpr (KIND == 1 && std::is_same<T, float>::value) {
+            // FP32 forms: r = (v^+)^2 with v = q/|q| is q^+ q^+ / |q|^2, so
+            // no square root is needed.  Products of two FP32 numbers are
+            // exact in FP64; the numerators and |q|^2 are formed in FP64,
+            // 1/|q|^2 is the hardware reciprocal refined by one Newton step
+            // (relative error ~1e-16), and r is rounded to FP32 once, as
+            // when it is computed from v in FP64.
+            const double q0 = qb.q0, q1 = qb.q1, q2 = qb.q2, q3 = qb.q3;
+            const double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+            if (!(n2 > 0.0)) continue;
+            const double i0 = __builtin_amdgcn_rcp(n2);
+            const double inv = fma(i0, fma(-n2, i0, 1.0), i0);
+            const double m2 = -2.0 * q0 * inv;
+            rt = {(float)((q0 * q0 - (q1 * q1 + q2 * q2 + q3 * q3)) * inv), (float)(m2 * q1), (float)(m2 * q2),
+                  (float)(m2 * q3)};
         } else {
-            if (!(k > 0.0)) continue;
-            const double ik = 1.0 / k;
-            const qt<double> vd = {qd.q0 * ik, -qd.q1 * ik, -qd.q2 * ik, -qd.q3 * ik};
-            r = qmul(vd, vd);
+            const qt<double> qd = {(double)qb.q0, (double)qb.q1, (double)qb.q2, (double)qb.q3};
+            const double k = sqrt(qnorm2(qd));
+            qt<double> r;
+            if constexpr (KIND == 0) {
+                const double alpha = 2.0 * a.beta * k / 3.0;
+                int8_t* log = a.accept_log ? a.accept_log + ((((int64_t)a.hb_offset * 4 + mu) * (2 * a.g.vh) + canon) * 3 + g) : nullptr;
+                if (!(alpha >= 1e-12)) {
+                    if (log) *log = -1;
+                    continue;
+                }
+                qt<double> x;
+                int t;
+                if constexpr (PREPARE) t = kp_prepared(alpha, a.nhit, d, g, first[g], x);
+                else t = kp(alpha, a.nhit, d, g, x);
+                if (log) *log = (int8_t)t;
+                if (t < 0) continue;
+                const double ik = 1.0 / k;
+                r = qmul_na(x, qt<double>{qd.q0 * ik, qd.q1 * ik, qd.q2 * ik, qd.q3 * ik});
+            } else {
+                if (!(k > 0.0)) continue;
+                const double ik = 1.0 / k;
+                const qt<double> vd = {qd.q0 * ik, -qd.q1 * ik, -qd.q2 * ik, -qd.q3 * ik};
+                r = qmul(vd, vd);
+            }
+            rt = {(T)r.q0, (T)r.q1, (T)r.q2, (T)r.q3};
         }
-        const qt<T> rt = {(T)r.q0, (T)r.q1, (T)r.q2, (T)r.q3};
         left_mul_block(U, ia, ib, rt);
         if (g < 2) left_mul_block(W, ia, ib, rt);
     }
