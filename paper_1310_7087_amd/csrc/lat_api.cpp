@@ -1462,6 +1462,16 @@ extern "C" int lat_batch_create(lat_batch_t* out, int n, const lat_desc* d, cons
     if (common) o = *common;
     if (o.rng != LAT_RNG_PHILOX) return fail(LAT_EUNSUPPORTED, "batches use the Philox generator");
     if (o.frozen != LAT_FROZEN_NONE) return fail(LAT_EUNSUPPORTED, "frozen links are not supported in a batch");
+    // every member is checked before the first device call
+    for (int i = 0; i < n; ++i) {
+        lat_options mo = o;
+        if (d[i].group == 2 && mo.storage == LAT_F32_C12) mo.storage = LAT_F32;
+        if (d[i].group == 2 && mo.storage == LAT_F64_C12) mo.storage = LAT_F64;
+        if (lat_device_bytes(d[i].group, d[i].Nx, d[i].Ny, d[i].Nz, d[i].Nt, &mo) == 0)
+            return fail(LAT_EINVAL, "batch member %d: invalid group, extents or storage", i);
+        if (!(d[i].beta >= 0.0) || d[i].beta > 1e6)
+            return fail(LAT_EINVAL, "batch member %d: beta must be finite and >= 0", i);
+    }
     lat_batch* b = new lat_batch();
     b->storage = o.storage;
     if (o.stream) {

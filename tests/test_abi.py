@@ -113,6 +113,24 @@ def test_maximum_sizes():
     assert e.value.code == P.EINVAL and "32-bit" in P.lib.lat_last_error().decode()
 
 
+@pytest.mark.parametrize("descs,kw,code", [
+    ([], {}, -1),
+    ([dict(group=3, dims=(4, 4, 4, 4), beta=5.7), dict(group=3, dims=(4, 5, 4, 4), beta=5.7)], {}, -1),
+    ([dict(group=4, dims=(4, 4, 4, 4), beta=5.7)], {}, -1),
+    ([dict(group=2, dims=(4, 4, 4, 4), beta=float("nan"))], {}, -1),
+    ([dict(group=3, dims=(4, 4, 4, 0), beta=5.7)], {}, -1),
+    ([dict(group=3, dims=(4, 4, 4, 4), beta=5.7)], {"rng": 0}, -7),
+])
+def test_batch_rejects_bad_members_without_a_device(descs, kw, code):
+    """An empty batch, a member with an odd or zero extent, a bad group or
+    coupling, or a generator other than Philox is refused before any device
+    call (this host has no GPU)."""
+    import paper_1310_7087_amd as P
+    with pytest.raises(P.LatError) as e:
+        P.Batch(descs, **kw)
+    assert e.value.code == code
+
+
 def test_batch_rejects_frozen_links_without_a_device():
     import paper_1310_7087_amd as P
     with pytest.raises(P.LatError) as e:
