@@ -940,36 +940,34 @@ struct event_guard {
     }
 };
 
-// Time `reps` compound sweeps of the current launch shape, launched
-// directly on the stream.  Every trial starts from the saved device state
-// `backup`, so that all candidate shapes are timed on the same links (the
-// heat bath's cost depends on them); the first trial only warms up (code
-// objects, caches).  The faster of the two timed trials.
+// Time `reps` compound sweeps of the current launch shape, captured as one
+// HIP graph and replayed, as lat_run runs them (with direct launches the
+// host's per-launch cost could hide differences of a few microseconds per
+// pass).  Every trial starts from the saved device state `backup`, so that
+// all candidate shapes are timed on the same links (the heat bath's cost
+// depends on them); the first replay only warms up (code objects, caches).
+// The faster of the two timed trials.
 int time_compound(lat_ctx* h, const char* backup, int n_hb, int n_or, int reps, double* ms) {
     event_guard g0, g1;
     HIP_TRY(hipEventCreate(&g0.e));
     HIP_TRY(hipEventCreate(&g1.e));
     const hipEvent_t e0 = g0.e, e1 = g1.e;
-    int rc = LAT_OK;
+    drop_graphs(h);  // a cached graph would hold the previous candidate's shape
+    hipGraphExec_t ex = nullptr;
+    int rc = get_graph(h, n_hb, n_or, false, reps, &ex);
     double best = 1e30;
     for (int trial = 0; trial < 3 && !rc; ++trial) {
-        if (hipMemcpyAsync(h->base, backup, h->lay.total, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) {
-            rc = fail(LAT_EDEVICE, "autotune restore");
-            break;
-        }
-        if (trial == 0) {  // graph capture and warm-up
-            rc = enqueue_sweep(h, n_hb, n_or);
-            continue;
-        }
-        hipError_t e = hipEventRecord(e0, h->stream);
-        for (int r = 0; r < reps && !rc && e == hipSuccess; ++r) rc = enqueue_sweep(h, n_hb, n_or);
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        hipError_t e = hipMemcpyAsync(h->base, backup, h->lay.total, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess && trial > 0) e = hipEventRecord(e0, h->stream);
+        if (e == hipSuccess) e = hipGraphLaunch(ex, h->stream);
+        if (e == hipSuccess && trial > 0) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         float t = 0.f;
-        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-        if (!rc && e != hipSuccess) rc = fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
-        if (!rc && t / reps < best) best = t / reps;
+        if (e == hipSuccess && trial > 0) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) rc = fail(LAT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
+        if (!rc && trial > 0 && t / reps < best) best = t / reps;
     }
+    drop_graphs(h);
     if (rc) return rc;
     *ms = best;
     return LAT_OK;
