@@ -54,3 +54,47 @@ def test_committed_valu_count_is_used_only_for_the_current_o4_kernel():
         assert per_hit is not None and 1.0 < per_hit < 10.0
     else:
         assert per_hit is None  # counters of an older kernel: reported as null
+
+
+def test_binned_error_matches_independent_samples():
+    """The binned standard error of the precision legs equals sigma/sqrt(n)
+    for independent samples (within the spread of a 50-bin estimate)."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+    x = rng.normal(0.25, 2.0, 100000)
+    m, e = bench.binned(x, 50)
+    assert abs(m - 0.25) < 5 * 2.0 / np.sqrt(x.size)
+    assert 0.7 < e / (2.0 / np.sqrt(x.size)) < 1.3
+
+
+def test_binned_error_sees_autocorrelation():
+    """For an AR(1) series with integrated autocorrelation time
+    (1 + a) / (1 - a) the binned error grows by its square root, which a
+    naive sigma/sqrt(n) would miss."""
+    import numpy as np
+    rng = np.random.default_rng(8)
+    a, n = 0.8, 200000
+    x = np.empty(n)
+    x[0] = 0.0
+    eps = rng.normal(0.0, 1.0, n)
+    for i in range(1, n):
+        x[i] = a * x[i - 1] + eps[i]
+    sigma = 1.0 / np.sqrt(1 - a * a)
+    tau = (1 + a) / (1 - a)
+    _, e = bench.binned(x, 50)
+    assert 0.7 < e / (sigma * np.sqrt(tau / n)) < 1.3
+
+
+def test_paired_difference_cancels_the_shared_part():
+    """Two coupled chains share most of their fluctuation: the paired error
+    of their difference reflects only the unshared part."""
+    import numpy as np
+    rng = np.random.default_rng(9)
+    n = 100000
+    shared = rng.normal(0.0, 10.0, n)
+    x = shared + rng.normal(1e-3, 0.1, n)
+    y = shared + rng.normal(0.0, 0.1, n)
+    d, e = bench.paired(x, y)
+    expect = np.sqrt(2) * 0.1 / np.sqrt(n)
+    assert 0.7 < e / expect < 1.3
+    assert abs(d - 1e-3) < 5 * expect
