@@ -1366,6 +1366,8 @@ int batch_build_table(lat_batch* b) {
         for (int i = 0; i < n; ++i)
             for (int tl = 0; tl < t[i].ntiles; ++tl) items.push_back({i, tl});
     }
+    // device buffers first, then the copies from these host vectors, which
+    // are waited for on every path before the vectors go out of scope
     if (items.size() > b->items_cap) {
         if (b->d_items) HIP_TRY(hipFree(b->d_items));
         b->d_items = nullptr;
@@ -1373,17 +1375,22 @@ int batch_build_table(lat_batch* b) {
         HIP_TRY(hipMalloc(&b->d_items, sizeof(BatchItem) * items.size()));
         b->items_cap = items.size();
     }
-    b->nitems = (int)items.size();
-    HIP_TRY(hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice,
-                           b->stream));
     if (!b->d_lats) HIP_TRY(hipMalloc(&b->d_lats, sizeof(BatchLat) * n));
     if (!b->d_counters) HIP_TRY(hipMalloc(&b->d_counters, sizeof(uint64_t*) * n));
     if (!b->d_work) HIP_TRY(hipMalloc(&b->d_work, sizeof(unsigned) * (n + 2)));
-    HIP_TRY(hipMemcpyAsync(b->d_lats, t.data(), sizeof(BatchLat) * n, hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->d_counters, ctr.data(), sizeof(uint64_t*) * n, hipMemcpyHostToDevice, b->stream));
-    std::vector<unsigned> zero(n + 2, 0);
-    HIP_TRY(hipMemcpyAsync(b->d_work, zero.data(), zero.size() * sizeof(unsigned), hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->nitems = (int)items.size();
+    const std::vector<unsigned> zero(n + 2, 0);
+    hipError_t e = hipMemcpyAsync(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_lats, t.data(), sizeof(BatchLat) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_counters, ctr.data(), sizeof(uint64_t*) * n, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_work, zero.data(), zero.size() * sizeof(unsigned), hipMemcpyHostToDevice, b->stream);
+    const hipError_t es = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return fail(LAT_EDEVICE, "batch work table: %s", hipGetErrorString(e));
     return LAT_OK;
 }
 
