@@ -336,14 +336,17 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site(
         const int64_t s_pn = site_step(a.g, cs, nu, +1).s;
         const int64_t s_mn = site_step(a.g, cs, nu, -1).s;
         const int64_t s_pmmn = site_step(a.g, cpm, nu, -1).s;
-        // With two stored rows, the first factor of each partial product
-        // is used without its third row: two rows of the product are
+        // With two stored rows, the first factor of a partial product can
+        // be used without its third row: two rows of the product are
         // formed and the third follows from them (the product is in SU(3)).
-        // Measured faster for both heat baths and the FP64 overrelaxation;
-        // the FP32 overrelaxation runs faster with the full products.
-        constexpr bool TR = ST::TWO_ROWS && (KIND == 0 || std::is_same<T, double>::value);
+        // Measured faster for both terms in the heat baths and the FP64
+        // overrelaxation; the FP32 overrelaxation is fastest with it in the
+        // forward term only (2%; in both terms 5% slower than in neither,
+        // from the extra live registers).
+        constexpr bool TRF = ST::TWO_ROWS;
+        constexpr bool TRB = ST::TWO_ROWS && (KIND == 0 || std::is_same<T, double>::value);
         const M f0 = [&] {
-            if constexpr (TR) return load_link_rows01<ST>(L, vp, q, nu, s_pm);
+            if constexpr (TRF) return load_link_rows01<ST>(L, vp, q, nu, s_pm);
             else return load_link<ST>(L, vp, q, nu, s_pm);
         }();
         const M f1 = [&] {  // U_mu(x + nu): staged in LDS or from memory
@@ -352,9 +355,9 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site(
         }();
         const M f2 = load_link<ST>(L, vp, p, nu, s);
         const M b0 = [&] {  // U_mu(x - nu)
-            if constexpr (LQ && TR) return ST::load_rows01(lq.lds, lq.nslots, lq.bwd[nu]);
+            if constexpr (LQ && TRB) return ST::load_rows01(lq.lds, lq.nslots, lq.bwd[nu]);
             else if constexpr (LQ) return ST::load(lq.lds, lq.nslots, lq.bwd[nu]);
-            else if constexpr (TR) return load_link_rows01<ST>(L, vp, q, mu, s_mn);
+            else if constexpr (TRB) return load_link_rows01<ST>(L, vp, q, mu, s_mn);
             else return load_link<ST>(L, vp, q, mu, s_mn);
         }();
         const M b1 = load_link<ST>(L, vp, p, nu, s_pmmn);
@@ -367,16 +370,20 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site(
                 for (int g = 0; g < 3; ++g) first[g] = kp_prepare(d, g);
             }
         }
-        if constexpr (TR) {
-            M fq, bq;
+        if constexpr (TRF) {
+            M fq;
             mul_na_rows01(fq, f0, f1);
             third_row(fq);
             mac_na(A, fq, f2);
+        } else {
+            mac_na(A, mul_na(f0, f1), f2);
+        }
+        if constexpr (TRB) {
+            M bq;
             mul_nn_rows01(bq, b0, b1);
             third_row(bq);
             mac_an(A, bq, b2);
         } else {
-            mac_na(A, mul_na(f0, f1), f2);
             mac_an(A, mul_nn(b0, b1), b2);
         }
     }
