@@ -979,10 +979,24 @@ __global__ void __launch_bounds__(256) meas_final(MeasArgs a, double* out, uint3
     const int64_t n[4] = {2 * (int64_t)a.nb_plaq, 2 * (int64_t)a.nb_plaq, a.nb_poly, a.nb_poly};
     const double* src[4] = {a.partial, a.partial + 2 * (int64_t)a.nb_plaq, a.partial + 4 * (int64_t)a.nb_plaq,
                             a.partial + 4 * (int64_t)a.nb_plaq + a.nb_poly};
+    // each thread sums its partials i = tid, tid + 256, ... in that order;
+    // eight of them are loaded before the first is added, so the loads are
+    // in flight together instead of one at a time
+    constexpr int U = 8;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         nsum acc = {0.0, 0.0};
-        for (int64_t i = tid; i < n[k]; i += 256) acc = nadd(acc, src[k][i]);
+        for (int64_t i0 = tid; i0 < n[k]; i0 += 256 * U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + 256 * u;
+                v[u] = i < n[k] ? src[k][i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + 256 * u < n[k]) acc = nadd(acc, v[u]);
+        }
         sh[k][tid] = acc;
     }
     __syncthreads();
