@@ -299,15 +299,16 @@ def run_large(P, sweeps: int = 40):
 
 def run_batch(P, sweeps: int = 10, precision_sweeps: int = 1000):
     """64 independent lattices (SU(2)/SU(3), 8^3x4 .. 24^3x6, coupling scan):
-    the FP32 batch launch against the same lattices run one by one in FP64
-    (the plain form) and against the FP64 batch."""
+    the FP32 batch launch (18-real, and 12-real for the SU(3) members)
+    against the same lattices run one by one in FP64 (the plain form) and
+    against the FP64 batch."""
     from inputs import batch_workloads
     ws = batch_workloads(64, seed=11)
     descs = [dict(group=w.group, dims=w.dims, beta=w.beta, flux=w.flux, seed=w.seed, start=w.start,
                   lattice_id=w.lattice_id) for w in ws]
     links = sum(4 * volume(w.dims) for w in ws)
     rates, shapes = {}, {}
-    for name, storage in (("f32_batched", P.F32), ("f64_batched", P.F64)):
+    for name, storage in (("f32_batched", P.F32), ("f32c12_batched", P.F32_C12), ("f64_batched", P.F64)):
         bt = P.Batch(descs, storage=storage)
         bt.run(20, N_HB, N_OR, measure=False)
         shapes[name] = bt.autotune(N_HB, N_OR)
@@ -326,18 +327,23 @@ def run_batch(P, sweeps: int = 10, precision_sweeps: int = 1000):
     rates["f64_one_by_one"] = sweeps * 5 * links / (time.perf_counter() - t0)
     for s in singles:
         s.close()
-    log(f"[batch] F32 batched {rates['f32_batched']:.3e}, F64 batched {rates['f64_batched']:.3e}, "
+    log(f"[batch] F32 batched {rates['f32_batched']:.3e}, F32 12-real batched {rates['f32c12_batched']:.3e}, "
+        f"F64 batched {rates['f64_batched']:.3e}, "
         f"F64 one by one {rates['f64_one_by_one']:.3e} link updates/s")
     # algorithmic bytes: 9 b per link update (4.5 V b per pass), b by group and storage
-    bpl = {("f32", 3): 72, ("f32", 2): 16, ("f64", 3): 144, ("f64", 2): 32}
+    # SU(2) members of the 12-real batch keep FP32 quaternions
+    bpl = {("f32", 3): 72, ("f32", 2): 16, ("f32c12", 3): 48, ("f32c12", 2): 16, ("f64", 3): 144, ("f64", 2): 32}
     frac = {}
-    for name in ("f32_batched", "f64_batched"):
-        per_update = sum(4 * volume(w.dims) * 9 * bpl[(name[:3], w.group)] for w in ws) / links
+    for name in ("f32_batched", "f32c12_batched", "f64_batched"):
+        form = name[:-len("_batched")]
+        per_update = sum(4 * volume(w.dims) * 9 * bpl[(form, w.group)] for w in ws) / links
         frac[name] = {"algorithmic_GBs": rates[name] * per_update / 1e9,
                       "hbm_fraction": rates[name] * per_update / 1e9 / HBM_PEAK_GBS}
     out = {"lattices": len(ws), "total_links": links, "sweeps": sweeps, "launch_shapes": shapes,
            "roofline": frac,
            "f32_batched_link_updates_per_s": rates["f32_batched"],
+           "f32c12_batched_link_updates_per_s": rates["f32c12_batched"],
+           "speedup_f32c12": rates["f32c12_batched"] / rates["f64_one_by_one"],
            "f64_batched_link_updates_per_s": rates["f64_batched"],
            "f64_one_by_one_link_updates_per_s": rates["f64_one_by_one"],
            "speedup": rates["f32_batched"] / rates["f64_one_by_one"]}
