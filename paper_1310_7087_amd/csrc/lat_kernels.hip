@@ -616,6 +616,18 @@ LAT_DEV void su2_site(const PassArgs& a, int64_t s) {
             for (int j = 0; j < 24; ++j) a.mrg[((int64_t)p * 25 + j) * vp + s] = d.lds[j * d.stride];
             a.mrg[((int64_t)p * 25 + 24) * vp + s] = d.c;
         }
+    } else if constexpr (std::is_same<T, float>::value) {
+        // FP32 storage: r = q^+ q^+ / |q|^2 from the exact FP64 products of
+        // the FP32 components, rounded to FP32 once (as for SU(3))
+        const double n2 = qd.q0 * qd.q0 + qd.q1 * qd.q1 + qd.q2 * qd.q2 + qd.q3 * qd.q3;
+        if (n2 > 0.0) {
+            const double i0 = __builtin_amdgcn_rcp(n2);
+            const double inv = fma(i0, fma(-n2, i0, 1.0), i0);
+            const double m2 = -2.0 * qd.q0 * inv;
+            r = {(qd.q0 * qd.q0 - (qd.q1 * qd.q1 + qd.q2 * qd.q2 + qd.q3 * qd.q3)) * inv, m2 * qd.q1, m2 * qd.q2,
+                 m2 * qd.q3};
+            apply = true;
+        }
     } else {
         if (k > 0.0) {
             const double ik = 1.0 / k;
