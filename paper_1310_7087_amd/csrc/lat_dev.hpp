@@ -669,6 +669,19 @@ struct st_f64 {  // SU(3), 18 doubles: 9 planes of (re, im)
     static constexpr int NP = 9;
     static constexpr int VB = 16;
     static constexpr bool TWO_ROWS = false;  // all three rows are stored
+    // rows 0 and 1 only (row 2 zero): the first factor of a two-row product
+    LAT_DEV static mat load_rows01(const char* base, int64_t plane_stride, int64_t s) {
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        mat m;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double2 v = ld_plane<double2>(base, pb, k, off);
+            m.e[k / 3][k % 3] = {v.x, v.y};
+        }
+        m.e[2][0] = m.e[2][1] = m.e[2][2] = {double(0), double(0)};
+        return m;
+    }
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
         const uint32_t off = (uint32_t)s * VB;
         const int64_t pb = plane_stride * VB;
@@ -694,6 +707,19 @@ struct st_f32 {  // SU(3), 18 floats: 9 planes of (re, im)
     static constexpr int NP = 9;
     static constexpr int VB = 8;
     static constexpr bool TWO_ROWS = false;
+    // rows 0 and 1 only (row 2 zero): the first factor of a two-row product
+    LAT_DEV static mat load_rows01(const char* base, int64_t plane_stride, int64_t s) {
+        const uint32_t off = (uint32_t)s * VB;
+        const int64_t pb = plane_stride * VB;
+        mat m;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float2 v = ld_plane<float2>(base, pb, k, off);
+            m.e[k / 3][k % 3] = {v.x, v.y};
+        }
+        m.e[2][0] = m.e[2][1] = m.e[2][2] = {float(0), float(0)};
+        return m;
+    }
     LAT_DEV static mat load(const char* base, int64_t plane_stride, int64_t s) {
         const uint32_t off = (uint32_t)s * VB;
         const int64_t pb = plane_stride * VB;

@@ -336,15 +336,23 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site(
         const int64_t s_pn = site_step(a.g, cs, nu, +1).s;
         const int64_t s_mn = site_step(a.g, cs, nu, -1).s;
         const int64_t s_pmmn = site_step(a.g, cpm, nu, -1).s;
-        // With two stored rows, the first factor of a partial product can
-        // be used without its third row: two rows of the product are
-        // formed and the third follows from them (the product is in SU(3)).
-        // Measured faster for both terms in the heat baths and the FP64
-        // overrelaxation; the FP32 overrelaxation is fastest with it in the
-        // forward term only (2%; in both terms 5% slower than in neither,
-        // from the extra live registers).
-        constexpr bool TRF = ST::TWO_ROWS;
-        constexpr bool TRB = ST::TWO_ROWS && (KIND == 0 || std::is_same<T, double>::value);
+        // Two-row products: the first factor of a partial product is used
+        // without its third row (for the 12-real forms its third row is not
+        // rebuilt, for the 18-real ones not loaded); two rows of the product
+        // are formed and the third follows from them (the product is in
+        // SU(3)).  Same-run timing on MI355X chose where: 12-real forms in
+        // both terms of the heat baths and the FP64 overrelaxation, in the
+        // forward term only of the FP32 overrelaxation (2%; both terms 5%
+        // slower than neither); 18-real forms in both terms (32^3x8: FP32
+        // OR 19.1 -> 17.8 us, FP64 OR 37.7 -> 35.5 us, heat baths 3% faster;
+        // 64^3x16 FP64: OR 669 -> 646 us, heat bath 773 -> 718 us).  With
+        // them the per-direction FP64 18-real overrelaxation kernel was far
+        // slower (37.7 -> 50.7 us), the one taking the direction at run time
+        // is not: that pass runs the latter (see launch_su3).  Every pass of
+        // a form, plain or staged, does the same arithmetic and gives the
+        // same links.
+        constexpr bool TRF = true;
+        constexpr bool TRB = !ST::TWO_ROWS || KIND == 0 || std::is_same<T, double>::value;
         // In the FP64 12-real heat bath the forward term is loaded and
         // accumulated before the backward term's links are requested, with
         // scheduling barriers that keep the compiler from hoisting them:
@@ -1333,7 +1341,10 @@ hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
             return hipGetLastError();
         }
     }
-    if constexpr (KIND == 1) {
+    // overrelaxation kernels specialised per direction, except for the FP64
+    // 18-real form, whose run-time-direction kernel is faster with the
+    // two-row products (su3_site)
+    if constexpr (KIND == 1 && !std::is_same<ST, st_f64>::value) {
         switch (a.mu) {
             case 0: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 0>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
             case 1: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 1>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
