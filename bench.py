@@ -232,15 +232,16 @@ def precision_leg(P, steps: int, therm: int = 200, forms=("f32c12", "f32", "f64c
     return out
 
 
-def precision_large(P, steps: int, therm: int = 200, seed: int = 23):
-    """FP32 12-real against FP64 on SU(3) 64^3 x 16 (beta 6.0, Haar start):
-    one coupled pair of chains (same start, same random numbers), `therm`
-    compound sweeps discarded, the paired per-sweep difference of each
-    observable over `steps` measured ones with a binned error (20 bins)."""
+def precision_large(P, steps: int, therm: int = 200, seed: int = 23, forms=("f32c12",)):
+    """FP32 12-real (and any other `forms`, e.g. the FP64 12-real control)
+    against FP64 on SU(3) 64^3 x 16 (beta 6.0, Haar start): chains coupled
+    to the FP64 one (same start, same random numbers), `therm` compound
+    sweeps discarded, the paired per-sweep difference of each observable
+    over `steps` measured ones with a binned error (20 bins)."""
     import numpy as np
     dims = (64, 64, 64, 16)
     series = {}
-    for form in ("f64", "f32c12"):
+    for form in ("f64",) + tuple(forms):
         t0 = time.perf_counter()
         lat = P.Lattice(3, dims, 6.0, 0, storage=storage_of(P, form), rng=P.RNG_PHILOX, seed=seed, start=P.HOT)
         plaq, poly = lat.run(therm + steps, N_HB, N_OR, measure_every=1)
@@ -251,14 +252,16 @@ def precision_large(P, steps: int, therm: int = 200, seed: int = 23):
     out = {"lattice": list(dims), "beta": 6.0, "start": "hot", "seed": seed, "steps": steps,
            "thermalisation": therm, "bins": 20, "bound": 1e-5,
            "f64_means": {k: dict(zip(("mean", "err"), binned(v, 20))) for k, v in series["f64"].items()}}
-    rows = {}
-    for k, v in series["f32c12"].items():
-        d, e = paired(v, series["f64"][k], 20)
-        rows[k] = {"delta": d, "err": e,
-                   "independent_chain_err": math.hypot(binned(v, 20)[1], binned(series["f64"][k], 20)[1])}
-    rows["P_within_bound"] = bool(abs(rows["P"]["delta"]) + 2 * rows["P"]["err"] <= 1e-5)
-    out["f32c12"] = rows
-    log(f"[precision 64^3x16] f32c12 - f64: <P> {rows['P']['delta']:.2e} +- {rows['P']['err']:.1e}")
+    for form in forms:
+        rows = {}
+        for k, v in series[form].items():
+            d, e = paired(v, series["f64"][k], 20)
+            rows[k] = {"delta": d, "err": e,
+                       "independent_chain_err": math.hypot(binned(v, 20)[1], binned(series["f64"][k], 20)[1])}
+        rows["P_within_bound"] = bool(abs(rows["P"]["delta"]) + 2 * rows["P"]["err"] <= 1e-5)
+        out[form] = rows
+        log(f"[precision 64^3x16] {form} - f64: <P> {rows['P']['delta']:.2e} +- {rows['P']['err']:.1e}, "
+            f"|L| {rows['absL']['delta']:.2e} +- {rows['absL']['err']:.1e}")
     return out
 
 
@@ -601,6 +604,9 @@ def main() -> int:
     ap.add_argument("--precision-large-steps", type=int, default=0,
                     help="measured compound sweeps of the FP32 12-real vs FP64 comparison on 64^3x16 "
                          "(0 skips it)")
+    ap.add_argument("--precision-large-forms", default="f32c12",
+                    help="forms compared with FP64 on 64^3x16 (f64c12 adds the FP64 12-real control)")
+    ap.add_argument("--precision-large-seed", type=int, default=23, help="seed of the 64^3x16 pair")
     ap.add_argument("--precision-seeds", default="3,4,5",
                     help="seeds of the independent replicas of the precision leg")
     ap.add_argument("--precision-only", action="store_true",
@@ -635,12 +641,14 @@ def main() -> int:
 
     seeds = tuple(int(x) for x in args.precision_seeds.split(",") if x.strip())
     pforms = tuple(x.strip() for x in args.precision_forms.split(",") if x.strip())
+    large_forms = tuple(x.strip() for x in args.precision_large_forms.split(",") if x.strip())
     if args.precision_only:
         res = {"workload": "su3_32^3x8_beta5.9_flux1_cold_philox_1hb4or"}
         if args.precision_steps > 0:
             res["precision"] = precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds)
         if args.precision_large_steps > 0:
-            res["precision_64x16"] = precision_large(P, args.precision_large_steps)
+            res["precision_64x16"] = precision_large(P, args.precision_large_steps, seed=args.precision_large_seed,
+                                                     forms=large_forms)
         if args.precision_sweeps > 0:
             from inputs import batch_workloads
             descs = [dict(group=w.group, dims=w.dims, beta=w.beta, flux=w.flux, seed=w.seed, start=w.start,
@@ -728,7 +736,8 @@ def main() -> int:
     if args.precision_steps > 0:
         out["precision"] = precision_leg(P, args.precision_steps, forms=pforms, seeds=seeds)
     if args.precision_large_steps > 0:
-        out["precision_64x16"] = precision_large(P, args.precision_large_steps)
+        out["precision_64x16"] = precision_large(P, args.precision_large_steps, seed=args.precision_large_seed,
+                                                     forms=large_forms)
     if not args.no_extras:
         out["su3_64x16"] = run_large(P)
         out["batch_64_lattices"] = run_batch(P, precision_sweeps=args.precision_sweeps)
