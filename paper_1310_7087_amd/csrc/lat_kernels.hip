@@ -1517,6 +1517,11 @@ static void batch_launch_typed(const BatchArgs& b, int mode, int grid, int block
         if (hb) {
             if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 0, true, -1>), g, t, 0, st, b, gp);
             else hipLaunchKernelGGL((batch_pass<ST3, ST2, 0, false, -1>), g, t, 0, st, b, gp);
+        } else if constexpr (std::is_same<ST3, st_f64>::value) {
+            // as for single lattices, the FP64 18-real overrelaxation takes
+            // the direction at run time (faster with the two-row products)
+            if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, true, -1>), g, t, 0, st, b, gp);
+            else hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, false, -1>), g, t, 0, st, b, gp);
         } else {
 #define LAT_BATCH_OR(M)                                                                          \
     if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, true, M>), g, t, 0, st, b, gp);          \
