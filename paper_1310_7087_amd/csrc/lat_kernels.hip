@@ -346,11 +346,11 @@ LAT_DEV void su3_site(const PassArgs& a, int64_t s, const lq_site& lq = lq_site(
         // slower than neither); 18-real forms in both terms (32^3x8: FP32
         // OR 19.1 -> 17.8 us, FP64 OR 37.7 -> 35.5 us, heat baths 3% faster;
         // 64^3x16 FP64: OR 669 -> 646 us, heat bath 773 -> 718 us).  With
-        // them the per-direction FP64 18-real overrelaxation kernel was far
-        // slower (37.7 -> 50.7 us), the one taking the direction at run time
-        // is not: that pass runs the latter (see launch_su3).  Every pass of
-        // a form, plain or staged, does the same arithmetic and gives the
-        // same links.
+        // them the per-direction overrelaxation kernels lost to those taking
+        // the direction at run time for every form but FP32 12-real (FP64
+        // 18-real OR 50.7 against 35.5 us; see launch_su3).  Every pass of a
+        // form, plain or staged, does the same arithmetic and gives the same
+        // links.
         constexpr bool TRF = true;
         constexpr bool TRB = !ST::TWO_ROWS || KIND == 0 || std::is_same<T, double>::value;
         // In the FP64 12-real heat bath the forward term is loaded and
@@ -1323,11 +1323,8 @@ hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
     if constexpr (RNG != LAT_RNG_RANLUX_I) {
         if (a.stage_lds) {
             const size_t lds = (size_t)a.stage_lds;
-            // overrelaxation of the compressed and FP32 forms runs best
-            // specialised per direction; the FP64 18-real form (whose
-            // specialised form needs more registers than a wave has) and the
-            // heat bath take the direction at run time
-            constexpr bool PER_MU = KIND == 1 && !std::is_same<ST, st_f64>::value;
+            // per-direction overrelaxation only for FP32 12-real, as below
+            constexpr bool PER_MU = KIND == 1 && std::is_same<ST, st_f32c12>::value;
             if constexpr (PER_MU) {
                 switch (a.mu) {
                     case 0: hipLaunchKernelGGL((su3_pass_lq<ST, KIND, RE, RNG, 0>), dim3(nb), dim3(block), lds, st, a); break;
@@ -1341,10 +1338,14 @@ hipError_t launch_su3(const PassArgs& a, int block, hipStream_t st) {
             return hipGetLastError();
         }
     }
-    // overrelaxation kernels specialised per direction, except for the FP64
-    // 18-real form, whose run-time-direction kernel is faster with the
-    // two-row products (su3_site)
-    if constexpr (KIND == 1 && !std::is_same<ST, st_f64>::value) {
+    // Overrelaxation specialised per direction only for FP32 12-real: with
+    // the two-row products (su3_site) the run-time-direction kernels of the
+    // other forms are faster (MI355X, same run, 32^3x8 OR pass: FP64 18-real
+    // 35.5 against 50.7 us, FP32 18-real 17.7 against 18.1 us, FP64 12-real
+    // 25.8 against 26.8 us plain and 24.6 against 25.0 us staged; FP32
+    // 12-real 13.46 against 13.24 us).  Heat baths always take it at run
+    // time (their straight-line form spills).
+    if constexpr (KIND == 1 && std::is_same<ST, st_f32c12>::value) {
         switch (a.mu) {
             case 0: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 0>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
             case 1: hipLaunchKernelGGL((su3_pass<ST, KIND, RE, RNG, 1>), dim3(nb), dim3(block), a.lds_reserve, st, a); break;
@@ -1517,9 +1518,11 @@ static void batch_launch_typed(const BatchArgs& b, int mode, int grid, int block
         if (hb) {
             if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 0, true, -1>), g, t, 0, st, b, gp);
             else hipLaunchKernelGGL((batch_pass<ST3, ST2, 0, false, -1>), g, t, 0, st, b, gp);
-        } else if constexpr (std::is_same<ST3, st_f64>::value) {
-            // as for single lattices, the FP64 18-real overrelaxation takes
-            // the direction at run time (faster with the two-row products)
+        } else if constexpr (!std::is_same<ST3, st_f32c12>::value) {
+            // as for single lattices, overrelaxation takes the direction at
+            // run time except in the FP32 12-real form (64-lattice scan:
+            // FP64 4.49 -> 4.98, FP32 10.61 -> 11.38, FP64 12-real
+            // 6.63 -> 6.98 1e9 link updates/s)
             if (re) hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, true, -1>), g, t, 0, st, b, gp);
             else hipLaunchKernelGGL((batch_pass<ST3, ST2, 1, false, -1>), g, t, 0, st, b, gp);
         } else {
