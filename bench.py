@@ -619,6 +619,9 @@ def main() -> int:
     ap.add_argument("--o4-only", action="store_true",
                     help="only run the O(4) model's lattices and print their JSON line")
     ap.add_argument("--o4-sizes", default="16,32,72", help="O(4) lattice extents L (L^4) to run")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only run the SU(3) 64^3x16 leg (after the --copy-mib calibration copy) and print "
+                         "its JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the lattice is resident on a single MI355X); "
@@ -671,6 +674,9 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"calibration copy of {args.copy_mib} MiB done")
         del src, dst
+    if args.large_only:
+        print(json.dumps({"su3_64x16": run_large(P)}), flush=True)
+        return 0
     copy_gbs = copy_bandwidth(torch)
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
