@@ -974,14 +974,18 @@ int time_compound(lat_ctx* h, const char* backup, int n_hb, int n_or, int reps, 
 }
 
 // Candidate launch shapes of a pass kernel: work-group size x work-group
-// order x occupancy cap, and for SU(3) the LDS-staged 4-D tiles that divide
-// the lattice and fit the LDS of a work-group.
+// order (z-slab per XCD, linear, reversed) x occupancy cap, and for SU(3)
+// the LDS-staged 4-D tiles that divide the lattice and fit the LDS of a
+// work-group.  Reversed order is searched because on MI355X it ran the FP64
+// overrelaxation pass of SU(3) 64^3x16 2% faster than linear (639 against
+// 648 us); one contiguous range per XCD (order 3) was slower at every size
+// and is left out.
 std::vector<pass_shape> shape_candidates(const lat_ctx* h) {
     std::vector<pass_shape> out;
     const int blocks[3] = {64, 128, 256};
     const int caps[4] = {-1, 1, 2, 3};
     for (int block : blocks)
-        for (int order = 0; order < 2; ++order)
+        for (int order = 0; order < 3; ++order)
             for (int cap : caps) {
                 pass_shape s;
                 s.block = block;

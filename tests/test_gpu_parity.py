@@ -384,7 +384,7 @@ def test_autotune_keeps_the_chain(tmp_path, monkeypatch):
         before = a.get_links()
         info0 = a.info()
         shape = a.autotune(1, 4)
-        assert shape["block_size"] in (64, 128, 256) and shape["tile_order"] in (0, 1, 4)
+        assert shape["block_size"] in (64, 128, 256) and shape["tile_order"] in (0, 1, 2, 4)
         kinds = a.launch_shapes()
         assert kinds["overrelaxation"]["block_size"] == shape["block_size"]
         assert np.array_equal(a.get_links(), before) and a.info() == info0
