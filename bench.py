@@ -619,6 +619,9 @@ def main() -> int:
     ap.add_argument("--o4-only", action="store_true",
                     help="only run the O(4) model's lattices and print their JSON line")
     ap.add_argument("--o4-sizes", default="16,32,72", help="O(4) lattice extents L (L^4) to run")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the 64-lattice batch leg, without its precision sweeps (after the "
+                         "--copy-mib calibration copy), and print its JSON line")
     ap.add_argument("--large-only", action="store_true",
                     help="only run the SU(3) 64^3x16 leg (after the --copy-mib calibration copy) and print "
                          "its JSON line")
@@ -676,6 +679,9 @@ def main() -> int:
         del src, dst
     if args.large_only:
         print(json.dumps({"su3_64x16": run_large(P)}), flush=True)
+        return 0
+    if args.batch_only:
+        print(json.dumps({"batch_64_lattices": run_batch(P, precision_sweeps=0)}), flush=True)
         return 0
     copy_gbs = copy_bandwidth(torch)
 
